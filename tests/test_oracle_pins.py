@@ -1,0 +1,334 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test fixes one part of the oracle by a route that does not reuse its
+code: complex-step and finite-difference derivatives (Squire & Trapp 1998),
+PyTorch float64 autograd on a textbook MLP (eq. 2.1 with the product of
+eq. 2.2 formed explicitly), closed-form solutions of eq. 4.1, exact
+properties of EIM/DEIM (eq. 2.7), the full-index-set reduction of eq. 2.8
+to the LRNR, and the closed form of Adam's first steps.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import lrnr_oracle as orc
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def tiny_case(seed=11, M=(2, 12, 10, 9, 1), rank=4, n=40):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    M = list(M)
+    net = wl.make_net(rng, M, wl.ranks(M, rank))
+    pts = wl.make_points(rng, n, 7, 5)
+    mu = np.array([3.0, 0.7, 1.3])
+    return net, pts, mu
+
+
+# ---------------------------------------------------------------- jets -----
+
+def test_jets_complex_step_x_t():
+    net, pts, _ = tiny_case()
+    xt = pts.xt_r.astype(np.float64)
+    jets = orc.lrnr_forward_jets(net, net.s, xt)
+    h = 1e-30
+    for comp, col in (("x", 0), ("t", 1)):
+        z = xt.astype(np.complex128)
+        z[:, col] += 1j * h
+        d = orc.lrnr_forward_jets(net, net.s, z)[0].imag / h
+        ref = jets[1 if comp == "x" else 2]
+        np.testing.assert_allclose(ref, d, rtol=1e-12, atol=1e-14)
+
+
+def test_jets_uxx_difference_of_complex_step():
+    net, pts, _ = tiny_case()
+    xt = pts.xt_r.astype(np.float64)
+    uxx = orc.lrnr_forward_jets(net, net.s, xt)[3]
+    h, d = 1e-4, 1e-30
+
+    def ux_cs(shift):
+        z = xt.astype(np.complex128)
+        z[:, 0] += shift + 1j * d
+        return orc.lrnr_forward_jets(net, net.s, z)[0].imag / d
+
+    fd = (ux_cs(h) - ux_cs(-h)) / (2 * h)
+    scale = np.abs(uxx).max()
+    np.testing.assert_allclose(uxx, fd, rtol=0, atol=1e-7 * scale)
+
+
+def _torch_case(net, pts, mu, cfg):
+    torch = pytest.importorskip("torch")
+    dt = torch.float64
+    U = [torch.tensor(u, dtype=dt) for u in net.U]
+    V = [torch.tensor(v, dtype=dt) for v in net.V]
+    b = [torch.tensor(x, dtype=dt, requires_grad=True) for x in net.b]
+    s = [torch.tensor(x, dtype=dt, requires_grad=True) for x in net.s]
+    L = len(U)
+
+    def u_of(x, t):
+        z = torch.stack([x, t], dim=-1)
+        for l in range(L):
+            W = U[l] @ torch.diag(s[l]) @ V[l].T
+            z = z @ W.T + b[l]
+            if l < L - 1:
+                z = torch.sin(z)
+        return z[..., 0]
+
+    x = torch.tensor(pts.xt_r[:, 0], dtype=dt, requires_grad=True)
+    t = torch.tensor(pts.xt_r[:, 1], dtype=dt, requires_grad=True)
+    u = u_of(x, t)
+    ux, = torch.autograd.grad(u.sum(), x, create_graph=True)
+    ut, = torch.autograd.grad(u.sum(), t, create_graph=True)
+    uxx, = torch.autograd.grad(ux.sum(), x, create_graph=True)
+    beta, nu, rho = (float(m) for m in mu)
+    res = ut + beta * ux - nu * uxx - rho * u * (1 - u)
+    x0 = torch.tensor(pts.x_0, dtype=dt)
+    tb = torch.tensor(pts.t_b, dtype=dt)
+    e0 = u_of(x0, torch.zeros_like(x0)) - torch.sin(x0)
+    eb = u_of(torch.zeros_like(tb), tb) - u_of(torch.full_like(tb, 2 * math.pi), tb)
+    loss = (cfg["w_r"] * (res ** 2).mean() + cfg["w_0"] * (e0 ** 2).mean()
+            + cfg["w_b"] * (eb ** 2).mean())
+    loss.backward()
+    jets = np.stack([u.detach().numpy(), ux.detach().numpy(), ut.detach().numpy(),
+                     uxx.detach().numpy()])
+    return (float(loss), jets, np.concatenate([x.grad.numpy() for x in s]),
+            np.concatenate([x.grad.numpy() for x in b]))
+
+
+def test_oracle_matches_torch_autograd_textbook_mlp():
+    net, pts, mu = tiny_case()
+    cfg = {"form": 0, "w_r": 1.0, "w_0": 2.0, "w_b": 0.5}
+    tl, tj, tgs, tgb = _torch_case(net, pts, mu, cfg)
+    jets = orc.lrnr_forward_jets(net, net.s, pts.xt_r)
+    np.testing.assert_allclose(jets, tj, rtol=1e-11, atol=1e-13)
+    l4, gs, gb = orc.lrnr_loss(net, net.s, mu, pts, cfg, with_grad=True)
+    assert abs(l4[0] - tl) <= 1e-12 * abs(tl)
+    np.testing.assert_allclose(gs, tgs, rtol=1e-10, atol=1e-13)
+    np.testing.assert_allclose(gb, tgb, rtol=1e-10, atol=1e-13)
+
+
+# ------------------------------------------------------------ residual -----
+
+def test_exact_zero_convection_residual():
+    """u = h(x - beta t) solves u_t + beta u_x = 0 whatever h is: a net whose
+    first layer sees only x - beta t must give a zero interior residual."""
+    beta = 10.0
+    rng = np.random.Generator(np.random.PCG64(5))
+    M = [2, 16, 16, 16, 1]
+    r = [1, 6, 6, 1]
+    net = wl.convection_net(rng, M, r, beta)
+    pts = wl.make_points(rng, 200, 10, 10)
+    jets = orc.lrnr_forward_jets(net, net.s, pts.xt_r)
+    res = orc.residual(jets[0], jets[1], jets[2], jets[3], [beta, 0.0, 0.0])
+    rms = math.sqrt(np.mean((beta * jets[1]) ** 2))
+    assert rms > 1e-3
+    assert np.abs(res).max() <= 1e-12 * rms
+
+
+def test_residual_closed_forms():
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0, 2 * math.pi, 100)
+    t = rng.uniform(0, 1, 100)
+    beta, nu = 4.0, 0.7
+    # u = exp(-nu t) sin(x - beta t) solves u_t + beta u_x - nu u_xx = 0
+    e = np.exp(-nu * t)
+    u = e * np.sin(x - beta * t)
+    ux = e * np.cos(x - beta * t)
+    ut = -nu * u - beta * ux
+    uxx = -u
+    assert np.abs(orc.residual(u, ux, ut, uxx, [beta, nu, 0.0])).max() < 1e-13
+    # logistic u(t) solves u_t = rho u (1 - u), no x dependence
+    rho, u0 = 2.5, 0.3
+    u = 1.0 / (1.0 + (1 - u0) / u0 * np.exp(-rho * t))
+    ut = rho * (1 - u0) / u0 * np.exp(-rho * t) * u * u
+    z = np.zeros_like(u)
+    assert np.abs(orc.residual(u, z, ut, z, [beta, 0.0, rho])).max() < 1e-13
+    # a wrong sign anywhere must show: the same data with mu_2 flipped fails
+    e = np.exp(-nu * t)
+    u = e * np.sin(x - beta * t)
+    ux = e * np.cos(x - beta * t)
+    assert np.abs(orc.residual(u, ux, -nu * u - beta * ux, -u, [beta, -nu, 0.0])).max() > 1e-2
+
+
+def test_loss_terms_brute_force_fsum():
+    """The interior/initial/boundary means, assembled point by point with
+    math.fsum from separately evaluated u at (x,0), (0,t) and (2 pi, t)."""
+    net, pts, mu = tiny_case()
+    cfg = {"form": 0, "w_r": 1.5, "w_0": 0.25, "w_b": 3.0}
+    l4, _, _ = orc.lrnr_loss(net, net.s, mu, pts, cfg)
+    jets = orc.lrnr_forward_jets(net, net.s, pts.xt_r)
+    res = orc.residual(jets[0], jets[1], jets[2], jets[3], mu)
+    interior = cfg["w_r"] * math.fsum(float(r) ** 2 for r in res) / len(res)
+    ic = []
+    for x in pts.x_0:
+        u = orc.lrnr_forward_jets(net, net.s, np.array([[x, 0.0]]))[0, 0]
+        ic.append((u - math.sin(float(x))) ** 2)
+    bc = []
+    for t in pts.t_b:
+        ul = orc.lrnr_forward_jets(net, net.s, np.array([[0.0, t]]))[0, 0]
+        ur = orc.lrnr_forward_jets(net, net.s, np.array([[2 * math.pi, t]]))[0, 0]
+        bc.append((ul - ur) ** 2)
+    ic_t = cfg["w_0"] * math.fsum(ic) / len(ic)
+    bc_t = cfg["w_b"] * math.fsum(bc) / len(bc)
+    np.testing.assert_allclose(l4[1:], [interior, ic_t, bc_t], rtol=1e-12)
+    assert abs(l4[0] - (interior + ic_t + bc_t)) <= 1e-12 * l4[0]
+
+
+# ------------------------------------------------------------ gradients ----
+
+def _complex_step_grad(fun, x0, h=1e-30):
+    g = np.zeros(len(x0))
+    for k in range(len(x0)):
+        z = x0.astype(np.complex128)
+        z[k] += 1j * h
+        g[k] = fun(z).imag / h
+    return g
+
+
+def test_grad_s_b_complex_step():
+    net, pts, mu = tiny_case(n=25)
+    cfg = {"form": 0, "w_r": 1.0, "w_0": 1.0, "w_b": 1.0}
+    _, gs, gb = orc.lrnr_loss(net, net.s, mu, pts, cfg, with_grad=True)
+    s0 = net.s_flat().astype(np.float64)
+    cs = _complex_step_grad(lambda z: orc.lrnr_loss(net, net.split_s(z), mu, pts, cfg)[0][0], s0)
+    np.testing.assert_allclose(gs, cs, rtol=1e-11, atol=1e-14)
+    b0 = np.concatenate(net.b).astype(np.float64)
+
+    def lb(z):
+        import copy
+        n2 = copy.copy(net)
+        out, o = [], 0
+        for x in net.b:
+            out.append(z[o:o + len(x)])
+            o += len(x)
+        n2.b = out
+        return orc.lrnr_loss(n2, net.s, mu, pts, cfg)[0][0]
+
+    cb = _complex_step_grad(lb, b0)
+    np.testing.assert_allclose(gb, cb, rtol=1e-11, atol=1e-14)
+
+
+def test_grad_l1_form_and_locality_fd():
+    net, pts, mu = tiny_case(n=25)
+    s0 = net.s_flat().astype(np.float64)
+    sref = s0 + np.linspace(-0.2, 0.2, len(s0)) + 0.013
+    cfg = {"form": 1, "w_r": 1.0, "w_0": 0.5, "w_b": 2.0, "lambda_loc": 0.3, "s_ref": sref}
+    _, gs, _ = orc.lrnr_loss(net, net.s, mu, pts, cfg, with_grad=True)
+    h = 1e-7
+    fd = np.zeros_like(s0)
+    for k in range(len(s0)):
+        sp, sm = s0.copy(), s0.copy()
+        sp[k] += h
+        sm[k] -= h
+        fd[k] = (orc.lrnr_loss(net, net.split_s(sp), mu, pts, cfg)[0][0]
+                 - orc.lrnr_loss(net, net.split_s(sm), mu, pts, cfg)[0][0]) / (2 * h)
+    np.testing.assert_allclose(gs, fd, rtol=1e-6, atol=1e-7)
+
+
+def test_chunked_oracle_equals_unchunked():
+    net, pts, mu = tiny_case(n=50)
+    cfg = {"form": 0, "w_r": 1.0, "w_0": 1.0, "w_b": 1.0}
+    a = orc.lrnr_loss(net, net.s, mu, pts, cfg, with_grad=True)
+    b = orc.lrnr_loss_chunked(net, net.s, mu, pts, cfg, chunk=16)
+    for x, y in zip(a, b):
+        np.testing.assert_allclose(x, y, rtol=1e-12, atol=1e-15)
+
+
+# ------------------------------------------------------------ FastLRNR -----
+
+def test_deim_hand_worked_example():
+    g = json.load(open(os.path.join(GOLD, "deim_4x2.json")))
+    Xi = np.array(g["Xi"])
+    assert list(orc.deim_indices(Xi)) == g["P"]
+
+
+def test_deim_permuted_identity_picks_the_permutation():
+    perm = [5, 2, 7, 0, 3]
+    Xi = np.zeros((8, 5))
+    for j, p in enumerate(perm):
+        Xi[p, j] = 1.0 + 0.1 * j
+    Xi[:, 1] += 0.3 * Xi[:, 0]        # lower-triangular mixing keeps the picks
+    Xi[:, 4] += 0.2 * Xi[:, 2] - 0.1 * Xi[:, 3]
+    assert list(orc.deim_indices(Xi)) == perm
+
+
+def test_deim_interpolation_and_error_bound():
+    rng = np.random.default_rng(7)
+    Z = rng.standard_normal((30, 12)) @ rng.standard_normal((12, 200))
+    Z += 1e-3 * rng.standard_normal(Z.shape)
+    Xi = orc.pod_basis(Z, 8)
+    P = orc.deim_indices(Xi)
+    assert len(set(P.tolist())) == 8
+    proj = Xi @ np.linalg.inv(Xi[P, :])
+    f = rng.standard_normal(30)
+    # interpolation: exact at the selected indices
+    np.testing.assert_allclose((proj @ f[P])[P], f[P], rtol=1e-12, atol=1e-12)
+    # reproduction: exact on span(Xi)
+    g = Xi @ rng.standard_normal(8)
+    np.testing.assert_allclose(proj @ g[P], g, rtol=1e-10, atol=1e-12)
+    # error bound of DEIM for orthonormal Xi
+    err = np.linalg.norm(f - proj @ f[P])
+    bound = np.linalg.norm(np.linalg.inv(Xi[P, :]), 2) * np.linalg.norm(f - Xi @ (Xi.T @ f))
+    assert err <= bound * (1 + 1e-10)
+    # Xi is orthonormal and spans the leading left singular subspace
+    np.testing.assert_allclose(Xi.T @ Xi, np.eye(8), atol=1e-12)
+
+
+def test_fastlrnr_full_index_set_is_lrnr():
+    net, pts, mu = tiny_case(M=(2, 12, 10, 9, 1), n=30)
+    rng = np.random.default_rng(1)
+    xt_snap = wl.uniform_points(rng, 64)
+    fast = orc.fastlrnr_build(net, [net.s], xt_snap, [12, 10, 9])
+    for P, M in zip(fast["P"], (12, 10, 9)):
+        assert sorted(P.tolist()) == list(range(M))
+    cfg = {"form": 0, "w_r": 1.0, "w_0": 1.0, "w_b": 1.0}
+    l_a, g_a, _ = orc.lrnr_loss(net, net.s, mu, pts, cfg, with_grad=True)
+    l_b, g_b = orc.fast_loss(net, fast, net.s, mu, pts, cfg, with_grad=True)
+    np.testing.assert_allclose(l_b, l_a, rtol=1e-10)
+    np.testing.assert_allclose(g_b, g_a, rtol=1e-9, atol=1e-12)
+    ja = orc.lrnr_forward_jets(net, net.s, pts.xt_r)
+    jb = orc.fast_forward_jets(net, fast, net.s, pts.xt_r)
+    np.testing.assert_allclose(jb, ja, rtol=1e-9, atol=1e-11)
+
+
+def test_fastlrnr_grad_complex_step():
+    net, pts, mu = tiny_case(n=20)
+    rng = np.random.default_rng(2)
+    fast = orc.fastlrnr_build(net, [net.s], wl.uniform_points(rng, 64), [6, 5, 4])
+    cfg = {"form": 0, "w_r": 1.0, "w_0": 1.0, "w_b": 1.0}
+    _, gs = orc.fast_loss(net, fast, net.s, mu, pts, cfg, with_grad=True)
+    s0 = net.s_flat().astype(np.float64)
+    cs = _complex_step_grad(
+        lambda z: orc.fast_loss(net, fast, net.split_s(z), mu, pts, cfg)[0][0], s0)
+    np.testing.assert_allclose(gs, cs, rtol=1e-11, atol=1e-14)
+
+
+def test_fastlrnr_jets_complex_step():
+    net, pts, _ = tiny_case(n=20)
+    rng = np.random.default_rng(2)
+    fast = orc.fastlrnr_build(net, [net.s], wl.uniform_points(rng, 64), [6, 5, 4])
+    xt = pts.xt_r.astype(np.float64)
+    j = orc.fast_forward_jets(net, fast, net.s, xt)
+    z = xt.astype(np.complex128)
+    z[:, 0] += 1e-30j
+    np.testing.assert_allclose(j[1], orc.fast_forward_jets(net, fast, net.s, z)[0].imag / 1e-30,
+                               rtol=1e-12, atol=1e-14)
+
+
+# ---------------------------------------------------------------- Adam -----
+
+def test_adam_closed_form_constant_gradient():
+    s = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -1e-3, 2.0])
+    m = np.zeros(3)
+    v = np.zeros(3)
+    lr, eps = 1e-3, 1e-8
+    for k in range(1, 6):
+        s, m, v = orc.adam_step(s, g, m, v, k, lr=lr, eps=eps)
+        # bias correction makes m_hat = g and v_hat = g^2 for a constant g
+        expect = np.array([1.0, -2.0, 0.5]) - k * lr * g / (np.abs(g) + eps)
+        np.testing.assert_allclose(s, expect, rtol=1e-12, atol=1e-15)
