@@ -1,0 +1,227 @@
+/*
+ * lrnr.h - C ABI of the MI355X (gfx950) LRNR / FastLRNR physics-informed hot path.
+ *
+ * The library evaluates a Low Rank Neural Representation (arXiv 2410.04001,
+ * Section 2.1, eq. 2.1-2.4) at collocation points together with its x-, t- and
+ * xx-derivative jets, forms the convection-diffusion-reaction residual loss
+ * (Section 4, eq. 4.1; loss forms of eq. 3.5-3.7) and back-propagates it to the
+ * coefficients s and the biases b.  The same entry points run the FastLRNR of
+ * Section 2.2 (eq. 2.6-2.8): a FastLRNR is an LRNR whose hidden widths are the
+ * reduced widths r_hat, with operators (U_hat, V_hat, b_hat) from the EIM/DEIM
+ * construction of eq. 2.7.
+ *
+ * Conventions shared by every function:
+ *  - Return value: LRNR_OK (0) or a negative status; no exception crosses the ABI.
+ *    lrnr_status_string() gives the text, including the HIP error of LRNR_EHIP.
+ *  - Pointers marked [dev] are device memory owned by the caller; [host] are
+ *    host memory.  The library never frees caller memory.
+ *  - stream: a hipStream_t passed as void* (NULL = the default stream).  Calls
+ *    are asynchronous on that stream; outputs are valid once it has completed.
+ *    Host pointers are read before the call returns.
+ *  - Determinism: for identical inputs the outputs are bitwise identical; all
+ *    reductions run in a fixed order (no floating-point atomics).
+ *  - Calls on distinct streams with distinct workspaces may run concurrently.
+ *  - Arithmetic is FP32 on the device; cross-block sums are FP64.
+ */
+#ifndef LRNR_H
+#define LRNR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LRNR_MAX_LAYERS 8     /* L: weight layers (L-1 hidden + 1 linear output) */
+#define LRNR_MAX_WIDTH 256    /* hidden widths M_l (or reduced widths r_hat_l)   */
+#define LRNR_MAX_RANK 32      /* ranks r_l                                        */
+
+enum {
+  LRNR_OK = 0,
+  LRNR_EINVAL = -1,       /* bad shape, rank, count or pointer                  */
+  LRNR_ENOMEM = -2,       /* workspace too small or device allocation failed    */
+  LRNR_EHIP = -3,         /* HIP runtime error (text via lrnr_status_string)    */
+  LRNR_ESINGULAR = -4,    /* POD/DEIM breakdown (rank-deficient snapshots)      */
+  LRNR_EUNSUPPORTED = -5  /* width/rank/depth above the compiled limits         */
+};
+
+/*
+ * An LRNR with frozen bases (eq. 2.4).  L weight layers, widths M[0..L] with
+ * M[0] = 2 (input (x, t)) and M[L] = 1 (scalar u); ranks r[1..L] (r[0] unused)
+ * with 1 <= r[l] <= min(M[l-1], M[l], LRNR_MAX_RANK).  Layer l computes
+ * z^l = sin(U^l diag(s^l) V^lT z^{l-1} + b^l) for l < L and the linear
+ * u = U^L diag(s^L) V^LT z^{L-1} + b^L (eq. 2.1 with eq. 2.2).
+ *  U [dev]: U^1..U^L concatenated, U^l row-major [M[l]][r[l]].
+ *  V [dev]: V^1..V^L concatenated, V^l row-major [M[l-1]][r[l]]  (the reading
+ *           of eq. 2.2 under which U diag(s) V^T has the shape of W^l).
+ *  b [dev]: b^1..b^L concatenated, b^l [M[l]].
+ * Coefficients s are passed separately as [r_total] = s^1..s^L concatenated.
+ */
+typedef struct lrnr_net {
+  int32_t L;
+  int32_t M[LRNR_MAX_LAYERS + 1];
+  int32_t r[LRNR_MAX_LAYERS + 1];
+  const float* U;
+  const float* V;
+  const float* b;
+} lrnr_net;
+
+/*
+ * Collocation points of one loss (eq. 4.1 on Omega = (0, 2 pi) x (0, 1)):
+ *  xt_r [dev] [n_r][2] interior (x, t) pairs -> residual
+ *           N[u; mu] = u_t + mu_1 u_x - mu_2 u_xx - mu_3 u (1 - u);
+ *  x_0  [dev] [n_0] abscissae of the initial line -> u(x, 0) - sin x;
+ *  t_b  [dev] [n_b] times of the periodic boundary -> u(0, t) - u(2 pi, t).
+ * Any count may be 0 (its pointer may then be NULL).
+ */
+typedef struct lrnr_points {
+  const float* xt_r;
+  int64_t n_r;
+  const float* x_0;
+  int64_t n_0;
+  const float* t_b;
+  int64_t n_b;
+} lrnr_points;
+
+/*
+ * Loss form.  With phi(e) = e^2 (form 0, eq. 3.5) or |e| (form 1, eq. 3.6):
+ *   loss = w_r mean phi(N) + w_0 mean phi(IC) + w_b mean phi(BC)
+ *          + lambda_loc * sum |s - s_ref|                     (eq. 3.7)
+ * The means run over n_r, n_0 and n_b points.  The subgradient of |e| at 0 is
+ * taken as 0.  s_ref [dev] [r_total] may be NULL when lambda_loc == 0.
+ */
+typedef struct lrnr_loss_cfg {
+  int32_t form;
+  float w_r, w_0, w_b;
+  float lambda_loc;
+  const float* s_ref;
+} lrnr_loss_cfg;
+
+/* Opaque FastLRNR handle: owns the device copies of U_hat, V_hat, b_hat, P. */
+typedef struct fastlrnr_handle fastlrnr_handle;
+
+/*
+ * Forward jets (Section 2.1 eq. 2.1-2.2, differentiated by the chain rule):
+ *  s    [dev] [r_total] coefficients
+ *  xt   [dev] [n][2]    points
+ *  jets [dev] [4][n]    out: u, u_x, u_t, u_xx (structure of arrays)
+ * n may be 0.  No workspace is needed.
+ */
+int32_t lrnr_forward_jets(const lrnr_net* net, const float* s, const float* xt,
+                          int64_t n, float* jets, void* stream);
+
+/* Values only: u [dev] [n] at xt [dev] [n][2] (u_FASTSOL grid evaluation of
+ * Section 3.2 when s holds the fast-phase coefficients). */
+int32_t lrnr_forward_value(const lrnr_net* net, const float* s, const float* xt,
+                           int64_t n, float* u, void* stream);
+
+/*
+ * Workspace bytes needed by lrnr_residual_loss / lrnr_grad_s for this net and
+ * these point counts (batch = number of instances; 1 for the single calls).
+ * Returns 0 when the net or counts are invalid.
+ */
+size_t lrnr_workspace_size(const lrnr_net* net, const lrnr_points* pts, int32_t batch);
+
+/*
+ * Physics-informed loss (eq. 3.5 / 3.6 / 3.7 with the residual of eq. 4.1):
+ *  mu   [dev] [3]  (mu_1, mu_2, mu_3) = (beta, nu, rho)
+ *  loss [dev] [4]  out: total, interior term, initial term, boundary term
+ *                  (terms include their weights; total adds the lambda term)
+ *  ws   [dev] workspace of at least lrnr_workspace_size() bytes, 256-B aligned.
+ */
+int32_t lrnr_residual_loss(const lrnr_net* net, const float* s, const float* mu,
+                           const lrnr_points* pts, const lrnr_loss_cfg* cfg,
+                           float* loss, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Loss and its gradient (reverse mode through the jets) with respect to the
+ * coefficients s (the fine-tuning problem of eq. 3.5) and the biases b:
+ *  grad_s [dev] [r_total]        out
+ *  grad_b [dev] [sum_l M[l]]     out, may be NULL
+ *  loss   [dev] [4]              out, may be NULL
+ */
+int32_t lrnr_grad_s(const lrnr_net* net, const float* s, const float* mu,
+                    const lrnr_points* pts, const lrnr_loss_cfg* cfg,
+                    float* grad_s, float* grad_b, float* loss,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Batched loss + gradient for B instances that share the net and the point
+ * set but have their own coefficients and PDE parameters:
+ *  s      [dev] [B][r_total]
+ *  mu     [dev] [B][3]
+ *  grad_s [dev] [B][r_total]  out
+ *  loss   [dev] [B][4]        out, may be NULL
+ *  s_ref in cfg, when used, is [dev] [B][r_total].
+ * Instance i's results equal those of lrnr_grad_s on instance i alone, bitwise.
+ */
+int32_t lrnr_grad_s_batched(const lrnr_net* net, int32_t B, const float* s,
+                            const float* mu, const lrnr_points* pts,
+                            const lrnr_loss_cfg* cfg, float* grad_s, float* loss,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * FastLRNR construction (Section 2.2, eq. 2.7; construction of Section 4):
+ * snapshots of the hidden states z^l at n_snap points for each of the n_s
+ * coefficient vectors, POD basis Xi^l (leading r_hat[l] left singular vectors,
+ * FP64), DEIM indices P^l (greedy, ties to the smallest index) and reduced
+ * operators U_hat^l = P^T U^l, b_hat^l = P^T b^l,
+ * V_hat^{l+1} = (V^{(l+1)T} Xi^l (P^T Xi^l)^{-1})^T.
+ *  s_snap  [dev]  [n_s][r_total]
+ *  xt_snap [dev]  [n_snap][2]
+ *  r_hat   [host] [L-1] reduced widths of hidden layers 1..L-1, each in
+ *                 [1, min(M[l], n_s * n_snap, LRNR_MAX_WIDTH)]
+ *  out     [host] receives the handle; free it with fastlrnr_destroy.
+ * Synchronises the stream (the selection runs on the device but its result
+ * sizes the handle).  The net's device arrays are not referenced afterwards.
+ */
+int32_t fastlrnr_build(const lrnr_net* net, const float* s_snap, int32_t n_s,
+                       const float* xt_snap, int64_t n_snap, const int32_t* r_hat,
+                       fastlrnr_handle** out, void* stream);
+
+/* Reduced net of a handle as an lrnr_net (widths r_hat, device pointers owned
+ * by the handle): usable with every lrnr_* entry point. */
+int32_t fastlrnr_get_net(const fastlrnr_handle* h, lrnr_net* out);
+
+/* DEIM indices P^1..P^{L-1} concatenated into host [sum_l r_hat[l]]. */
+int32_t fastlrnr_get_indices(const fastlrnr_handle* h, int32_t* P);
+
+/*
+ * SPInProp: loss and gradient with respect to s of the FastLRNR (eq. 2.8)
+ * physics-informed loss (eq. 3.5 or 3.6 with the locality term of eq. 3.7).
+ * Arguments as lrnr_grad_s; the workspace is sized by lrnr_workspace_size on
+ * the net returned by fastlrnr_get_net.
+ */
+int32_t fastlrnr_grad_s(const fastlrnr_handle* h, const float* s, const float* mu,
+                        const lrnr_points* pts, const lrnr_loss_cfg* cfg,
+                        float* grad_s, float* loss, void* ws, size_t ws_bytes,
+                        void* stream);
+
+int32_t fastlrnr_destroy(fastlrnr_handle* h);
+
+/*
+ * Fused Adam step (Kingma & Ba; the optimiser of Section 4) on n coefficients,
+ * in place, bias-corrected with the 1-based step count:
+ *  s, m, v [dev] [n] updated; g [dev] [n] gradient.
+ */
+int32_t lrnr_adam_step(float* s, float* m, float* v, const float* g, int64_t n,
+                       int32_t step, float lr, float beta1, float beta2, float eps,
+                       void* stream);
+
+/*
+ * Measurement aid: the next launch of the fused loss/gradient kernel made by
+ * this thread (from lrnr_residual_loss, lrnr_grad_s, lrnr_grad_s_batched or
+ * fastlrnr_grad_s) is bracketed by hipEventRecord(start) and
+ * hipEventRecord(stop) on the call's stream.  start and stop are hipEvent_t
+ * passed as void*; NULL for both cancels a pending request.
+ */
+int32_t lrnr_time_next_fused(void* start_event, void* stop_event);
+
+/* Text of a status code (thread-local detail for LRNR_EHIP / LRNR_EINVAL). */
+const char* lrnr_status_string(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LRNR_H */

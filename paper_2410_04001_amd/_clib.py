@@ -1,0 +1,100 @@
+"""ctypes view of include/lrnr.h and loader of the in-tree liblrnr.so.
+
+Loading fails loudly when the library has not been built: there is no other
+implementation behind these names.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblrnr.so")
+
+MAX_LAYERS = 8
+MAX_WIDTH = 256
+MAX_RANK = 32
+
+OK, EINVAL, ENOMEM, EHIP, ESINGULAR, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+
+
+class LrnrNet(C.Structure):
+    _fields_ = [
+        ("L", C.c_int32),
+        ("M", C.c_int32 * (MAX_LAYERS + 1)),
+        ("r", C.c_int32 * (MAX_LAYERS + 1)),
+        ("U", C.c_void_p),
+        ("V", C.c_void_p),
+        ("b", C.c_void_p),
+    ]
+
+
+class LrnrPoints(C.Structure):
+    _fields_ = [
+        ("xt_r", C.c_void_p), ("n_r", C.c_int64),
+        ("x_0", C.c_void_p), ("n_0", C.c_int64),
+        ("t_b", C.c_void_p), ("n_b", C.c_int64),
+    ]
+
+
+class LrnrLossCfg(C.Structure):
+    _fields_ = [
+        ("form", C.c_int32),
+        ("w_r", C.c_float), ("w_0", C.c_float), ("w_b", C.c_float),
+        ("lambda_loc", C.c_float),
+        ("s_ref", C.c_void_p),
+    ]
+
+
+P = C.c_void_p
+I32, I64, F32, SZ = C.c_int32, C.c_int64, C.c_float, C.c_size_t
+NETP, PTSP, CFGP = C.POINTER(LrnrNet), C.POINTER(LrnrPoints), C.POINTER(LrnrLossCfg)
+
+# name -> (restype, argtypes); the exported surface of include/lrnr.h
+SIGNATURES = {
+    "lrnr_forward_jets": (I32, [NETP, P, P, I64, P, P]),
+    "lrnr_forward_value": (I32, [NETP, P, P, I64, P, P]),
+    "lrnr_workspace_size": (SZ, [NETP, PTSP, I32]),
+    "lrnr_residual_loss": (I32, [NETP, P, P, PTSP, CFGP, P, P, SZ, P]),
+    "lrnr_grad_s": (I32, [NETP, P, P, PTSP, CFGP, P, P, P, P, SZ, P]),
+    "lrnr_grad_s_batched": (I32, [NETP, I32, P, P, PTSP, CFGP, P, P, P, SZ, P]),
+    "fastlrnr_build": (I32, [NETP, P, I32, P, I64, C.POINTER(I32), C.POINTER(P), P]),
+    "fastlrnr_get_net": (I32, [P, NETP]),
+    "fastlrnr_get_indices": (I32, [P, C.POINTER(I32)]),
+    "fastlrnr_grad_s": (I32, [P, P, P, PTSP, CFGP, P, P, P, SZ, P]),
+    "fastlrnr_destroy": (I32, [P]),
+    "lrnr_adam_step": (I32, [P, P, P, P, I64, I32, F32, F32, F32, F32, P]),
+    "lrnr_time_next_fused": (I32, [P, P]),
+    "lrnr_status_string": (C.c_char_p, [I32]),
+}
+
+_lib = None
+
+
+class LrnrError(RuntimeError):
+    def __init__(self, status, where):
+        msg = lib().lrnr_status_string(status).decode()
+        super().__init__(f"{where}: status {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    """The loaded library; raises if it is missing (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -m paper_2410_04001_amd.build_lib`")
+        h = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(h, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = h
+    return _lib
+
+
+def check(status, where):
+    if status != OK:
+        raise LrnrError(status, where)

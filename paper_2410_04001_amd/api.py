@@ -1,0 +1,318 @@
+"""Torch-facing wrappers of the C ABI (argument marshalling only).
+
+Tensors must be float32 CUDA (ROCm) tensors; calls run on torch's current
+stream.  Every computation happens inside liblrnr.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _clib as cl
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(x, device):
+    t = torch.as_tensor(x, dtype=torch.float32, device=device)
+    return t.contiguous()
+
+
+class DeviceNet:
+    """An LRNR in device memory: widths M[0..L], ranks r[1..L] and the packed
+    factors of include/lrnr.h."""
+
+    def __init__(self, M, r, U, V, b, device="cuda", _keep=None):
+        self.M = [int(m) for m in M]
+        self.r = [int(x) for x in r]          # r_1..r_L
+        self.L = len(self.r)
+        self.U = _dev(U, device) if not isinstance(U, int) else U
+        self.V = _dev(V, device) if not isinstance(V, int) else V
+        self.b = _dev(b, device) if not isinstance(b, int) else b
+        self._keep = _keep
+        self._c = cl.LrnrNet()
+        self._c.L = self.L
+        for l, m in enumerate(self.M):
+            self._c.M[l] = m
+        for l, x in enumerate(self.r, start=1):
+            self._c.r[l] = x
+        self._c.U = self.U if isinstance(self.U, int) else self.U.data_ptr()
+        self._c.V = self.V if isinstance(self.V, int) else self.V.data_ptr()
+        self._c.b = self.b if isinstance(self.b, int) else self.b.data_ptr()
+
+    @classmethod
+    def from_net(cls, net, device="cuda"):
+        """From any object with M, r and packed() -> (U, V, b, s) host arrays."""
+        U, V, b, _ = net.packed()
+        return cls(net.M, net.r, U, V, b, device)
+
+    @property
+    def r_total(self):
+        return sum(self.r)
+
+    @property
+    def b_total(self):
+        return sum(self.M[1:])
+
+    def c(self):
+        return C.byref(self._c)
+
+
+class DevicePoints:
+    def __init__(self, xt_r, x_0, t_b, device="cuda"):
+        self.xt_r = _dev(np.asarray(xt_r, np.float32).reshape(-1, 2), device)
+        self.x_0 = _dev(np.asarray(x_0, np.float32).reshape(-1), device)
+        self.t_b = _dev(np.asarray(t_b, np.float32).reshape(-1), device)
+        self._c = cl.LrnrPoints(
+            self.xt_r.data_ptr() if self.xt_r.numel() else None, self.xt_r.shape[0],
+            self.x_0.data_ptr() if self.x_0.numel() else None, self.x_0.shape[0],
+            self.t_b.data_ptr() if self.t_b.numel() else None, self.t_b.shape[0])
+
+    @classmethod
+    def from_points(cls, pts, device="cuda"):
+        return cls(pts.xt_r, pts.x_0, pts.t_b, device)
+
+    @property
+    def counts(self):
+        return self.xt_r.shape[0], self.x_0.shape[0], self.t_b.shape[0]
+
+    def c(self):
+        return C.byref(self._c)
+
+
+class LossCfg:
+    def __init__(self, form=0, w_r=1.0, w_0=1.0, w_b=1.0, lambda_loc=0.0, s_ref=None):
+        self.s_ref = s_ref
+        self._c = cl.LrnrLossCfg(int(form), float(w_r), float(w_0), float(w_b),
+                                 float(lambda_loc),
+                                 None if s_ref is None else s_ref.data_ptr())
+
+    def c(self):
+        return C.byref(self._c)
+
+
+class Workspace:
+    """A device byte buffer, grown on demand and reused across calls."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes):
+        nbytes = max(int(nbytes), 256)
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        return self.buf
+
+    def ptr_size(self, nbytes):
+        b = self.get(nbytes)
+        addr = b.data_ptr()
+        pad = (-addr) % 256
+        return C.c_void_p(addr + pad), b.numel() - pad
+
+
+_default_ws = {}
+
+
+def _ws(device):
+    key = str(device)
+    if key not in _default_ws:
+        _default_ws[key] = Workspace(device)
+    return _default_ws[key]
+
+
+def workspace_size(net, pts, batch=1):
+    n = cl.lib().lrnr_workspace_size(net.c(), pts.c(), int(batch))
+    if n == 0:
+        raise cl.LrnrError(cl.EINVAL, "lrnr_workspace_size")
+    return n
+
+
+def forward_jets(net, s, xt):
+    n = xt.shape[0]
+    out = torch.empty((4, n), dtype=torch.float32, device=xt.device)
+    cl.check(cl.lib().lrnr_forward_jets(net.c(), _p(s), _p(xt), n, _p(out), _stream()),
+             "lrnr_forward_jets")
+    return out
+
+
+def forward_value(net, s, xt):
+    n = xt.shape[0]
+    out = torch.empty((n,), dtype=torch.float32, device=xt.device)
+    cl.check(cl.lib().lrnr_forward_value(net.c(), _p(s), _p(xt), n, _p(out), _stream()),
+             "lrnr_forward_value")
+    return out
+
+
+def residual_loss(net, s, mu, pts, cfg, ws=None):
+    ws = ws or _ws(s.device)
+    wp, wn = ws.ptr_size(workspace_size(net, pts))
+    loss = torch.empty(4, dtype=torch.float32, device=s.device)
+    cl.check(cl.lib().lrnr_residual_loss(net.c(), _p(s), _p(mu), pts.c(), cfg.c(), _p(loss),
+                                         wp, wn, _stream()), "lrnr_residual_loss")
+    return loss
+
+
+def grad_s(net, s, mu, pts, cfg, with_b=True, ws=None):
+    ws = ws or _ws(s.device)
+    wp, wn = ws.ptr_size(workspace_size(net, pts))
+    gs = torch.empty(net.r_total, dtype=torch.float32, device=s.device)
+    gb = torch.empty(net.b_total, dtype=torch.float32, device=s.device) if with_b else None
+    loss = torch.empty(4, dtype=torch.float32, device=s.device)
+    cl.check(cl.lib().lrnr_grad_s(net.c(), _p(s), _p(mu), pts.c(), cfg.c(), _p(gs), _p(gb),
+                                  _p(loss), wp, wn, _stream()), "lrnr_grad_s")
+    return gs, gb, loss
+
+
+def grad_s_batched(net, s, mu, pts, cfg, ws=None):
+    B = s.shape[0]
+    ws = ws or _ws(s.device)
+    wp, wn = ws.ptr_size(workspace_size(net, pts, B))
+    gs = torch.empty((B, net.r_total), dtype=torch.float32, device=s.device)
+    loss = torch.empty((B, 4), dtype=torch.float32, device=s.device)
+    cl.check(cl.lib().lrnr_grad_s_batched(net.c(), B, _p(s), _p(mu), pts.c(), cfg.c(), _p(gs),
+                                          _p(loss), wp, wn, _stream()), "lrnr_grad_s_batched")
+    return gs, loss
+
+
+class HipEvent:
+    """A timing hipEvent_t made through the HIP runtime (torch's Event will
+    not report the time of an event recorded outside torch)."""
+
+    _hip = None
+
+    def __init__(self):
+        if HipEvent._hip is None:
+            h = C.CDLL("libamdhip64.so")
+            h.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+            h.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+            h.hipEventDestroy.argtypes = [C.c_void_p]
+            h.hipEventRecord.argtypes = [C.c_void_p, C.c_void_p]
+            HipEvent._hip = h
+        self.ev = C.c_void_p()
+        if HipEvent._hip.hipEventCreate(C.byref(self.ev)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+
+    def record(self):
+        HipEvent._hip.hipEventRecord(self.ev, _stream())
+
+    def elapsed_ms(self, end):
+        out = C.c_float()
+        rc = HipEvent._hip.hipEventElapsedTime(C.byref(out), self.ev, end.ev)
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed ({rc})")
+        return out.value
+
+    def __del__(self):
+        try:
+            if self.ev.value:
+                HipEvent._hip.hipEventDestroy(self.ev)
+        except Exception:
+            pass
+
+
+def download(ptr, n):
+    """Copy n floats from a raw device pointer (e.g. the operators a FastLRNR
+    handle owns) into a host numpy array."""
+    if HipEvent._hip is None:
+        HipEvent()
+    h = HipEvent._hip
+    h.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    torch.cuda.synchronize()
+    out = np.empty(n, np.float32)
+    rc = h.hipMemcpy(out.ctypes.data, C.c_void_p(ptr), 4 * n, 2)  # device to host
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed ({rc})")
+    return out
+
+
+def time_next_fused(start, stop):
+    """Bracket the next fused-kernel launch of this thread with two HipEvent
+    objects (recorded on the call's stream by the library)."""
+    cl.check(cl.lib().lrnr_time_next_fused(start.ev, stop.ev), "lrnr_time_next_fused")
+
+
+def adam_step(s, m, v, g, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    cl.check(cl.lib().lrnr_adam_step(_p(s), _p(m), _p(v), _p(g), s.numel(), int(step),
+                                     float(lr), float(beta1), float(beta2), float(eps),
+                                     _stream()), "lrnr_adam_step")
+
+
+class FastLRNR:
+    """A FastLRNR built on the device by fastlrnr_build (eq. 2.7); its reduced
+    net runs through the same entry points as the LRNR."""
+
+    def __init__(self, net, s_snap, xt_snap, r_hat):
+        L = net.L
+        if np.isscalar(r_hat):
+            r_hat = [int(r_hat)] * (L - 1)
+        self.r_hat = [int(x) for x in r_hat]
+        rh = (C.c_int32 * (L - 1))(*self.r_hat)
+        h = C.c_void_p()
+        s_snap = s_snap.reshape(-1, net.r_total).contiguous()
+        cl.check(cl.lib().fastlrnr_build(net.c(), _p(s_snap), s_snap.shape[0], _p(xt_snap),
+                                         xt_snap.shape[0], rh, C.byref(h), _stream()),
+                 "fastlrnr_build")
+        self._h = h
+        cnet = cl.LrnrNet()
+        cl.check(cl.lib().fastlrnr_get_net(h, C.byref(cnet)), "fastlrnr_get_net")
+        self.net = DeviceNet(list(cnet.M)[:L + 1], list(cnet.r)[1:L + 1], int(cnet.U),
+                             int(cnet.V), int(cnet.b), device=s_snap.device, _keep=self)
+
+    def operators(self):
+        """Host copies of the reduced factors (U_hat^l, V_hat^{l+1}, b_hat^l per
+        hidden layer) unpacked from the handle's net."""
+        n = self.net
+        nU = sum(n.M[l] * n.r[l - 1] for l in range(1, n.L + 1))
+        nV = sum(n.M[l - 1] * n.r[l - 1] for l in range(1, n.L + 1))
+        nb = sum(n.M[1:])
+        U, V, b = download(n.U, nU), download(n.V, nV), download(n.b, nb)
+        Uh, Vh, bh = [], [], []
+        ou, ov, ob = 0, 2 * n.r[0], 0
+        for l in range(1, n.L):
+            w, rl, ro = n.M[l], n.r[l - 1], n.r[l]
+            Uh.append(U[ou:ou + w * rl].reshape(w, rl))
+            bh.append(b[ob:ob + w])
+            Vh.append(V[ov:ov + w * ro].reshape(w, ro))
+            ou += w * rl
+            ob += w
+            ov += w * ro
+        return {"U_hat": Uh, "V_hat": Vh, "b_hat": bh}
+
+    def indices(self):
+        tot = sum(self.r_hat)
+        buf = (C.c_int32 * tot)()
+        cl.check(cl.lib().fastlrnr_get_indices(self._h, buf), "fastlrnr_get_indices")
+        out, o = [], 0
+        for r in self.r_hat:
+            out.append(np.array(buf[o:o + r], dtype=np.int64))
+            o += r
+        return out
+
+    def grad_s(self, s, mu, pts, cfg, ws=None):
+        ws = ws or _ws(s.device)
+        wp, wn = ws.ptr_size(workspace_size(self.net, pts))
+        gs = torch.empty(self.net.r_total, dtype=torch.float32, device=s.device)
+        loss = torch.empty(4, dtype=torch.float32, device=s.device)
+        cl.check(cl.lib().fastlrnr_grad_s(self._h, _p(s), _p(mu), pts.c(), cfg.c(), _p(gs),
+                                          _p(loss), wp, wn, _stream()), "fastlrnr_grad_s")
+        return gs, loss
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            cl.lib().fastlrnr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,40 @@
+// Dispatch of the fused kernel over the compiled rank tiles; the kernel body is
+// in lrnr_fused_impl.h and each tile is instantiated in its own source file.
+#include "lrnr_internal.h"
+
+namespace lrnr {
+
+template <int RP>
+hipError_t launch_rp(int mode, const KNet& net, const KInst& inst, const KGrid& grid,
+                     hipStream_t stream);
+
+size_t fused_lds_bytes(int RP, int Wmax_p) {
+  const size_t floats = (size_t)Wmax_p * RP * 2 + Wmax_p + RP + (size_t)kWaves * Wmax_p +
+                        (size_t)kWaves * RP + kWaves * 4;
+  return floats * sizeof(float);
+}
+
+int padded_rank(int rmax) {
+  if (rmax <= 4) return 4;
+  if (rmax <= 8) return 8;
+  if (rmax <= 16) return 16;
+  if (rmax <= 20) return 20;
+  if (rmax <= 24) return 24;
+  if (rmax <= 32) return 32;
+  return -1;
+}
+
+hipError_t launch_fused(int RP, int mode, const KNet& net, const KInst& inst,
+                        const KGrid& grid, hipStream_t stream) {
+  switch (RP) {
+    case 4: return launch_rp<4>(mode, net, inst, grid, stream);
+    case 8: return launch_rp<8>(mode, net, inst, grid, stream);
+    case 16: return launch_rp<16>(mode, net, inst, grid, stream);
+    case 20: return launch_rp<20>(mode, net, inst, grid, stream);
+    case 24: return launch_rp<24>(mode, net, inst, grid, stream);
+    case 32: return launch_rp<32>(mode, net, inst, grid, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace lrnr
