@@ -34,9 +34,10 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-# The AGPR-copy rewrite pass of this LLVM crashes on the rank-32 gradient
-# kernel under the VGPR-form option, so that tile is built without it.
-NO_VGPR_FORM = {"lrnr_fused_rp32.hip"}
+# The AGPR-copy rewrite pass of this LLVM crashes on the rank-24 and rank-32
+# gradient kernels under the VGPR-form option, so those tiles are built
+# without it.
+NO_VGPR_FORM = {"lrnr_fused_rp24.hip", "lrnr_fused_rp32.hip"}
 
 
 def _flags(src):

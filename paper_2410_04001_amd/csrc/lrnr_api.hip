@@ -103,7 +103,7 @@ int32_t check_cfg(const lrnr_loss_cfg* cfg) {
 
 struct Plan {
   KGrid grid;
-  size_t off_partials, off_red1, off_ckpt, total;
+  size_t off_partials, off_red1, off_ckpt, off_flags, total;
   int nchunk;
 };
 
@@ -127,6 +127,8 @@ Plan make_plan(const KNet& k, int RP, int Wmax_p, const lrnr_points* pts, int B,
   off = align256(off + (size_t)B * p.nchunk * g.P * sizeof(double));
   p.off_ckpt = off;
   off = align256(off + (size_t)B * g.G_inst * kWaves * g.ckpt_per_wave * sizeof(float));
+  p.off_flags = off;
+  off = align256(off + (grad ? (size_t)B * g.G_inst * sizeof(int) : 0));
   p.total = std::max(off, (size_t)256);  // 0 is reserved for "invalid arguments"
   return p;
 }
@@ -171,6 +173,7 @@ int32_t run_loss(const lrnr_net* net, int B, const float* s, const float* mu,
   char* base = static_cast<char*>(ws);
   p.grid.partials = reinterpret_cast<float*>(base + p.off_partials);
   p.grid.ckpt = grad ? reinterpret_cast<float*>(base + p.off_ckpt) : nullptr;
+  p.grid.flags = grad ? reinterpret_cast<int*>(base + p.off_flags) : nullptr;
   KInst in = make_inst(s, mu, pts, cfg);
   hipStream_t hs = static_cast<hipStream_t>(stream);
   if (p.grid.G_inst > 0) {

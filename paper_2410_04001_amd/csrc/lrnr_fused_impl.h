@@ -37,21 +37,91 @@ __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
 
 __device__ __forceinline__ f4 zero4() { return f4{0.f, 0.f, 0.f, 0.f}; }
 
-// Sum each of the four components of v over the 64 lanes.  On return the lanes
-// of 16-lane row q hold the total of component sum4_component(q*16).
-__device__ __forceinline__ float wave_sum4(f4 v, int lane) {
-  const bool hi32 = lane & 32;
-  const float k01 = hi32 ? v[1] : v[0], p01 = hi32 ? v[0] : v[1];
-  const float k23 = hi32 ? v[3] : v[2], p23 = hi32 ? v[2] : v[3];
-  const float r01 = k01 + __shfl_xor(p01, 32);
-  const float r23 = k23 + __shfl_xor(p23, 32);
-  const bool hi16 = lane & 16;
-  float r = (hi16 ? r23 : r01) + __shfl_xor(hi16 ? r01 : r23, 16);
-  r += __shfl_xor(r, 8);
-  r += __shfl_xor(r, 4);
-  r += __shfl_xor(r, 2);
-  r += __shfl_xor(r, 1);
-  return r;
+// ---------------------------------------------------------------------------
+// sin and cos of one argument, branch-free.  Cody & Waite reduction by pi/2
+// split into three FP32 parts (P1 = fl(pi/2), P2 = fl(pi/2 - P1),
+// P3 = fl(pi/2 - P1 - P2)), applied with fused multiply-adds, then the Taylor
+// polynomials of sin (to degree 11) and cos (to degree 10) on [-pi/4, pi/4],
+// whose truncation errors there are below 1e-10.  Absolute error below 7.1e-8
+// for |x| <= kFastRange; larger arguments take ocml's sincosf (sin/cos policy
+// below).
+// ---------------------------------------------------------------------------
+constexpr float kFastRange = 1.0e6f;
+constexpr float kTwoOverPi = 0.63661974668502807617f;
+constexpr float kP1 = 1.57079637050628662109f;
+constexpr float kP2 = -4.37113882867379300296e-08f;
+constexpr float kP3 = -1.71512451000588191836e-15f;
+constexpr float kS3 = -1.0f / 6.0f, kS5 = 1.0f / 120.0f, kS7 = -1.0f / 5040.0f;
+constexpr float kS9 = 1.0f / 362880.0f, kS11 = -1.0f / 39916800.0f;
+constexpr float kC2 = -0.5f, kC4 = 1.0f / 24.0f, kC6 = -1.0f / 720.0f;
+constexpr float kC8 = 1.0f / 40320.0f, kC10 = -1.0f / 3628800.0f;
+
+__device__ __forceinline__ void sincos_fast(float x, float& s, float& c) {
+  const float k = __builtin_rintf(x * kTwoOverPi);
+  float r = __builtin_fmaf(-k, kP1, x);
+  r = __builtin_fmaf(-k, kP2, r);
+  r = __builtin_fmaf(-k, kP3, r);
+  const float r2 = r * r;
+  float ps = __builtin_fmaf(r2, kS11, kS9);
+  ps = __builtin_fmaf(r2, ps, kS7);
+  ps = __builtin_fmaf(r2, ps, kS5);
+  ps = __builtin_fmaf(r2, ps, kS3);
+  const float sn = __builtin_fmaf(r2 * r, ps, r);
+  float pc = __builtin_fmaf(r2, kC10, kC8);
+  pc = __builtin_fmaf(r2, pc, kC6);
+  pc = __builtin_fmaf(r2, pc, kC4);
+  pc = __builtin_fmaf(r2, pc, kC2);
+  const float cs = __builtin_fmaf(r2, pc, 1.0f);
+  const int q = (int)k;  // quadrant; two's complement bits give q mod 4
+  const float a = (q & 1) ? cs : sn;
+  const float b = (q & 1) ? sn : cs;
+  s = (q & 2) ? -a : a;
+  c = ((q + 1) & 2) ? -b : b;
+}
+
+template <bool ACC>
+__device__ __forceinline__ void sincos_sel(float x, float& s, float& c) {
+  if constexpr (ACC)
+    sincosf(x, &s, &c);
+  else
+    sincos_fast(x, s, c);
+}
+
+// How a kernel instance evaluates sin/cos:
+//  SC_REDO  fast path; a wave that met |a| > kFastRange redoes the layer with
+//           ocml's sincosf (forward-only modes, where registers are plentiful);
+//  SC_TRACK fast path only; the largest |a| is tracked and reported so that a
+//           following SC_ACC launch recomputes the flagged workgroups;
+//  SC_ACC   ocml's sincosf throughout.
+enum SinCos { SC_REDO = 0, SC_TRACK = 1, SC_ACC = 2 };
+
+// ---------------------------------------------------------------------------
+// Wave reduction of four values per lane.  Lanes 32-63 of one value swap with
+// lanes 0-31 of another (v_permlane32_swap), then odd 16-lane rows with even
+// rows (v_permlane16_swap), then a row sum by DPP row rotations.  On return
+// every lane of 16-lane row q holds the 64-lane total of component
+// sum4_component(16 q).
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float wave_sum4(f4 v, int /*lane*/) {
+  const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[0]), __float_as_uint(v[1]),
+                                                  false, false);
+  const float t01 = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+  const auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2]), __float_as_uint(v[3]),
+                                                  false, false);
+  const float t23 = __uint_as_float(q[0]) + __uint_as_float(q[1]);
+  const auto w = __builtin_amdgcn_permlane16_swap(__float_as_uint(t01), __float_as_uint(t23),
+                                                  false, false);
+  float x = __uint_as_float(w[0]) + __uint_as_float(w[1]);
+  x += dpp_mov<0x128>(x);  // row_ror:8
+  x += dpp_mov<0x124>(x);  // row_ror:4
+  x += dpp_mov<0x122>(x);  // row_ror:2
+  x += dpp_mov<0x121>(x);  // row_ror:1
+  return x;
 }
 
 __device__ __forceinline__ int sum4_component(int lane) {
@@ -59,62 +129,186 @@ __device__ __forceinline__ int sum4_component(int lane) {
 }
 
 // ---------------------------------------------------------------------------
-// One hidden layer, forward: y (s-scaled in place) -> yo = V^T sin-jets(U y + b)
+// Contraction pieces for one group of four neurons w0..w0+3.  In every MFMA
+// the B operand is the lane's own point value, the A operand a 4-vector of
+// factor entries broadcast from LDS.
 // ---------------------------------------------------------------------------
-template <int NJ, int RGM, int RGI, int RGO>
+
+// a_c = U[w0..w0+3] (s*y_c) (+ b for the value jet)
+template <int NJ, int RGM, int RGI>
+__device__ __forceinline__ void u_side(const float* __restrict__ Us, const float* __restrict__ bs,
+                                       int w0, int li, const f4 (&y)[NJ][RGM], f4 (&a)[NJ]) {
+  constexpr int KI = 4 * RGI;
+  a[0] = *reinterpret_cast<const f4*>(bs + w0);
+#pragma unroll
+  for (int c = 1; c < NJ; ++c) a[c] = zero4();
+  const float* urow = Us + (w0 + li) * KI;
+#pragma unroll
+  for (int g = 0; g < RGI; ++g) {
+    const f4 u4 = *reinterpret_cast<const f4*>(urow + 4 * g);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int c = 0; c < NJ; ++c) a[c] = mfma4(u4[kk], y[c][g][kk], a[c]);
+  }
+}
+
+// yo_c += V[w0..w0+3]^T z_c
+template <int NJ, int RGM, int RGO>
+__device__ __forceinline__ void v_side(const float* __restrict__ Vs, int w0, int li,
+                                       const f4 (&z)[NJ], f4 (&yo)[NJ][RGM]) {
+  constexpr int KO = 4 * RGO;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float* vrow = Vs + (w0 + j) * KO;
+#pragma unroll
+    for (int g = 0; g < RGO; ++g) {
+      const float v = vrow[4 * g + li];
+#pragma unroll
+      for (int c = 0; c < NJ; ++c) yo[c][g] = mfma4(v, z[c][j], yo[c][g]);
+    }
+  }
+}
+
+// zb_c = V[w0..w0+3] yb_c
+template <int NJ, int RGM, int RGO>
+__device__ __forceinline__ void v_rev(const float* __restrict__ Vs, int w0, int li,
+                                      const f4 (&yb)[NJ][RGM], f4 (&zb)[NJ]) {
+  constexpr int KO = 4 * RGO;
+#pragma unroll
+  for (int c = 0; c < NJ; ++c) zb[c] = zero4();
+  const float* vrow = Vs + (w0 + li) * KO;
+#pragma unroll
+  for (int g = 0; g < RGO; ++g) {
+    const f4 v4 = *reinterpret_cast<const f4*>(vrow + 4 * g);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int c = 0; c < NJ; ++c) zb[c] = mfma4(v4[kk], yb[c][g][kk], zb[c]);
+  }
+}
+
+// wb_c += U[w0..w0+3]^T ab_c
+template <int NJ, int RGM, int RGI>
+__device__ __forceinline__ void ut_side(const float* __restrict__ Us, int w0, int li,
+                                        const f4 (&ab)[NJ], f4 (&wb)[NJ][RGM]) {
+  constexpr int KI = 4 * RGI;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float* ucol = Us + (w0 + j) * KI;
+#pragma unroll
+    for (int g = 0; g < RGI; ++g) {
+      const float u = ucol[4 * g + li];
+#pragma unroll
+      for (int c = 0; c < NJ; ++c) wb[c][g] = mfma4(u, ab[c][j], wb[c][g]);
+    }
+  }
+}
+
+// Scheduling hint for a pipelined loop body whose first NM MFMAs do not depend
+// on the body's VALU work: pair each with two VALU instructions, so that the
+// matrix core and the vector ALU of the (single) wave on a SIMD overlap.
+template <int NM>
+__device__ __forceinline__ void interleave() {
+#pragma unroll
+  for (int i = 0; i < NM; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
+  }
+}
+
+// z jets = sin jets of a (value, d/dx, d/dt, d2/dx2); tracks max |a_v|
+template <int NJ, bool ACC>
+__device__ __forceinline__ void sigma_fwd(const f4 (&a)[NJ], f4 (&z)[NJ], float& amax) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float sn, cs;
+    sincos_sel<ACC>(a[0][j], sn, cs);
+    amax = fmaxf(amax, fabsf(a[0][j]));
+    z[0][j] = sn;
+    if constexpr (NJ == 4) {
+      const float ax = a[1][j];
+      z[1][j] = cs * ax;
+      z[2][j] = cs * a[2][j];
+      z[3][j] = cs * a[3][j] - sn * ax * ax;
+    }
+  }
+}
+
+// adjoints of the a jets from those of the z jets
+template <int NJ, bool ACC>
+__device__ __forceinline__ void sigma_bwd(const f4 (&a)[NJ], const f4 (&zb)[NJ], f4 (&ab)[NJ],
+                                          float& amax) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float sn, cs;
+    sincos_sel<ACC>(a[0][j], sn, cs);
+    amax = fmaxf(amax, fabsf(a[0][j]));
+    if constexpr (NJ == 4) {
+      const float ax = a[1][j], at = a[2][j], axx = a[3][j];
+      const float zv = zb[0][j], zx = zb[1][j], zt = zb[2][j], zxx = zb[3][j];
+      ab[3][j] = cs * zxx;
+      ab[2][j] = cs * zt;
+      ab[1][j] = cs * zx - 2.f * sn * ax * zxx;
+      ab[0][j] = cs * zv - sn * (ax * zx + at * zt + axx * zxx) - cs * ax * ax * zxx;
+    } else {
+      ab[0][j] = cs * zb[0][j];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One hidden layer, forward: ys = s * y (in place), yo = V^T sin-jets(U ys + b).
+// The loop is software-pipelined: the U-side MFMAs of the next neuron group
+// are issued next to the VALU sin-jet work of the current one.  Returns the
+// largest |a_v| seen (to select the accurate sin/cos path if needed).
+// ---------------------------------------------------------------------------
+template <int NJ, int RGM, int RGI, int RGO, bool ACC>
+__device__ __forceinline__ float layer_fwd_pass(const float* __restrict__ Us,
+                                                const float* __restrict__ Vs,
+                                                const float* __restrict__ bs, int Wp, int li,
+                                                const f4 (&ys)[NJ][RGM], f4 (&yo)[NJ][RGM]) {
+#pragma unroll
+  for (int c = 0; c < NJ; ++c)
+#pragma unroll
+    for (int g = 0; g < RGO; ++g) yo[c][g] = zero4();
+  float amax = 0.f;
+  f4 a[NJ], z[NJ];
+  u_side<NJ, RGM, RGI>(Us, bs, 0, li, ys, a);
+  for (int w0 = 0; w0 < Wp - 4; w0 += 4) {
+    f4 an[NJ];
+    u_side<NJ, RGM, RGI>(Us, bs, w0 + 4, li, ys, an);
+    sigma_fwd<NJ, ACC>(a, z, amax);
+    v_side<NJ, RGM, RGO>(Vs, w0, li, z, yo);
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) a[c] = an[c];
+    interleave<NJ * 4 * RGI>();
+  }
+  sigma_fwd<NJ, ACC>(a, z, amax);
+  v_side<NJ, RGM, RGO>(Vs, Wp - 4, li, z, yo);
+  return amax;
+}
+
+template <int NJ, int RGM, int RGI, int RGO, int SC>
 __device__ __forceinline__ void layer_fwd(const float* __restrict__ Us,
                                           const float* __restrict__ Vs,
                                           const float* __restrict__ bs,
                                           const float* __restrict__ ss, int Wp, int li,
-                                          f4 (&y)[NJ][RGM], f4 (&yo)[NJ][RGM]) {
-  constexpr int KI = 4 * RGI, KO = 4 * RGO;
+                                          f4 (&y)[NJ][RGM], f4 (&yo)[NJ][RGM], float& amax) {
 #pragma unroll
   for (int g = 0; g < RGI; ++g) {
     const f4 s4 = *reinterpret_cast<const f4*>(ss + 4 * g);
 #pragma unroll
     for (int c = 0; c < NJ; ++c) y[c][g] *= s4;
   }
-#pragma unroll
-  for (int c = 0; c < NJ; ++c)
-#pragma unroll
-    for (int g = 0; g < RGO; ++g) yo[c][g] = zero4();
-
-  for (int w0 = 0; w0 < Wp; w0 += 4) {
-    f4 a[NJ];
-    a[0] = *reinterpret_cast<const f4*>(bs + w0);
-#pragma unroll
-    for (int c = 1; c < NJ; ++c) a[c] = zero4();
-    const float* urow = Us + (w0 + li) * KI;
-#pragma unroll
-    for (int g = 0; g < RGI; ++g) {
-      const f4 u4 = *reinterpret_cast<const f4*>(urow + 4 * g);
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-        for (int c = 0; c < NJ; ++c) a[c] = mfma4(u4[kk], y[c][g][kk], a[c]);
-    }
-    f4 z[NJ];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      float sn, cs;
-      sincosf(a[0][j], &sn, &cs);
-      z[0][j] = sn;
-      if constexpr (NJ == 4) {
-        const float ax = a[1][j];
-        z[1][j] = cs * ax;
-        z[2][j] = cs * a[2][j];
-        z[3][j] = cs * a[3][j] - sn * ax * ax;
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const float* vrow = Vs + (w0 + j) * KO;
-#pragma unroll
-      for (int g = 0; g < RGO; ++g) {
-        const float v = vrow[4 * g + li];
-#pragma unroll
-        for (int c = 0; c < NJ; ++c) yo[c][g] = mfma4(v, z[c][j], yo[c][g]);
-      }
+  if constexpr (SC == SC_ACC) {
+    layer_fwd_pass<NJ, RGM, RGI, RGO, true>(Us, Vs, bs, Wp, li, y, yo);
+  } else {
+    const float m = layer_fwd_pass<NJ, RGM, RGI, RGO, false>(Us, Vs, bs, Wp, li, y, yo);
+    amax = fmaxf(amax, m);
+    if constexpr (SC == SC_REDO) {
+      if (__builtin_expect(__any(!(m <= kFastRange)), 0))
+        layer_fwd_pass<NJ, RGM, RGI, RGO, true>(Us, Vs, bs, Wp, li, y, yo);
     }
   }
 }
@@ -122,82 +316,71 @@ __device__ __forceinline__ void layer_fwd(const float* __restrict__ Us,
 // ---------------------------------------------------------------------------
 // One hidden layer, reverse: recompute a = U (s*y) + b, pull yb = dL/dy^{l+1}
 // back through V and the sin jets, write the layer's dL/db row, and return
-// wb = U^T abar (so that dL/ds = sum_c wb * y and dL/dy^l = s * wb).
+// wb = U^T abar (so that dL/ds = sum_c wb * y and dL/dy^l = s * wb).  The
+// U-side and V-side MFMAs of the next group overlap the current group's VALU
+// adjoint work.
 // ---------------------------------------------------------------------------
-template <int NJ, int RGM, int RGI, int RGO>
+template <int NJ, int RGM, int RGI, int RGO, bool ACC>
+__device__ __forceinline__ float layer_bwd_pass(const float* __restrict__ Us,
+                                                const float* __restrict__ Vs,
+                                                const float* __restrict__ bs, int Wp, int li,
+                                                int lane, const f4 (&ys)[NJ][RGM],
+                                                const f4 (&yb)[NJ][RGM], f4 (&wb)[NJ][RGM],
+                                                float* __restrict__ bbar_row) {
+#pragma unroll
+  for (int c = 0; c < NJ; ++c)
+#pragma unroll
+    for (int g = 0; g < RGI; ++g) wb[c][g] = zero4();
+  const int comp = sum4_component(lane);
+  float amax = 0.f;
+  f4 a[NJ], zb[NJ], ab[NJ];
+  u_side<NJ, RGM, RGI>(Us, bs, 0, li, ys, a);
+  v_rev<NJ, RGM, RGO>(Vs, 0, li, yb, zb);
+  for (int w0 = 0; w0 < Wp - 4; w0 += 4) {
+    f4 an[NJ], zbn[NJ];
+    u_side<NJ, RGM, RGI>(Us, bs, w0 + 4, li, ys, an);
+    v_rev<NJ, RGM, RGO>(Vs, w0 + 4, li, yb, zbn);
+    sigma_bwd<NJ, ACC>(a, zb, ab, amax);
+    const float bsum = wave_sum4(ab[0], lane);
+    if ((lane & 15) == 0) bbar_row[w0 + comp] = bsum;
+    ut_side<NJ, RGM, RGI>(Us, w0, li, ab, wb);
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) {
+      a[c] = an[c];
+      zb[c] = zbn[c];
+    }
+    interleave<NJ * 4 * (RGI + RGO)>();
+  }
+  sigma_bwd<NJ, ACC>(a, zb, ab, amax);
+  const float bsum = wave_sum4(ab[0], lane);
+  if ((lane & 15) == 0) bbar_row[Wp - 4 + comp] = bsum;
+  ut_side<NJ, RGM, RGI>(Us, Wp - 4, li, ab, wb);
+  return amax;
+}
+
+template <int NJ, int RGM, int RGI, int RGO, int SC>
 __device__ __forceinline__ void layer_bwd(const float* __restrict__ Us,
                                           const float* __restrict__ Vs,
                                           const float* __restrict__ bs,
                                           const float* __restrict__ ss, int Wp, int li,
                                           int lane, f4 (&y)[NJ][RGM],
                                           const f4 (&yb)[NJ][RGM], f4 (&wb)[NJ][RGM],
-                                          float* __restrict__ bbar_row) {
-  constexpr int KI = 4 * RGI, KO = 4 * RGO;
+                                          float* __restrict__ bbar_row, float& amax) {
 #pragma unroll
   for (int g = 0; g < RGI; ++g) {
     const f4 s4 = *reinterpret_cast<const f4*>(ss + 4 * g);
 #pragma unroll
     for (int c = 0; c < NJ; ++c) y[c][g] *= s4;
   }
-#pragma unroll
-  for (int c = 0; c < NJ; ++c)
-#pragma unroll
-    for (int g = 0; g < RGI; ++g) wb[c][g] = zero4();
-  const int comp = sum4_component(lane);
-
-  for (int w0 = 0; w0 < Wp; w0 += 4) {
-    f4 a[NJ];
-    a[0] = *reinterpret_cast<const f4*>(bs + w0);
-#pragma unroll
-    for (int c = 1; c < NJ; ++c) a[c] = zero4();
-    const float* urow = Us + (w0 + li) * KI;
-#pragma unroll
-    for (int g = 0; g < RGI; ++g) {
-      const f4 u4 = *reinterpret_cast<const f4*>(urow + 4 * g);
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-        for (int c = 0; c < NJ; ++c) a[c] = mfma4(u4[kk], y[c][g][kk], a[c]);
-    }
-    f4 zb[NJ];
-#pragma unroll
-    for (int c = 0; c < NJ; ++c) zb[c] = zero4();
-    const float* vrow = Vs + (w0 + li) * KO;
-#pragma unroll
-    for (int g = 0; g < RGO; ++g) {
-      const f4 v4 = *reinterpret_cast<const f4*>(vrow + 4 * g);
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-        for (int c = 0; c < NJ; ++c) zb[c] = mfma4(v4[kk], yb[c][g][kk], zb[c]);
-    }
-    f4 ab[NJ];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      float sn, cs;
-      sincosf(a[0][j], &sn, &cs);
-      if constexpr (NJ == 4) {
-        const float ax = a[1][j], at = a[2][j], axx = a[3][j];
-        const float zv = zb[0][j], zx = zb[1][j], zt = zb[2][j], zxx = zb[3][j];
-        ab[3][j] = cs * zxx;
-        ab[2][j] = cs * zt;
-        ab[1][j] = cs * zx - 2.f * sn * ax * zxx;
-        ab[0][j] = cs * zv - sn * (ax * zx + at * zt + axx * zxx) - cs * ax * ax * zxx;
-      } else {
-        ab[0][j] = cs * zb[0][j];
-      }
-    }
-    const float bsum = wave_sum4(ab[0], lane);
-    if ((lane & 15) == 0) bbar_row[w0 + comp] = bsum;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const float* ucol = Us + (w0 + j) * KI;
-#pragma unroll
-      for (int g = 0; g < RGI; ++g) {
-        const float u = ucol[4 * g + li];
-#pragma unroll
-        for (int c = 0; c < NJ; ++c) wb[c][g] = mfma4(u, ab[c][j], wb[c][g]);
-      }
+  if constexpr (SC == SC_ACC) {
+    layer_bwd_pass<NJ, RGM, RGI, RGO, true>(Us, Vs, bs, Wp, li, lane, y, yb, wb, bbar_row);
+  } else {
+    const float m =
+        layer_bwd_pass<NJ, RGM, RGI, RGO, false>(Us, Vs, bs, Wp, li, lane, y, yb, wb, bbar_row);
+    amax = fmaxf(amax, m);
+    if constexpr (SC == SC_REDO) {
+      if (__builtin_expect(__any(!(m <= kFastRange)), 0))
+        layer_bwd_pass<NJ, RGM, RGI, RGO, true>(Us, Vs, bs, Wp, li, lane, y, yb, wb, bbar_row);
     }
   }
 }
@@ -256,34 +439,37 @@ __device__ __forceinline__ void input_jets(const KNet& net, float x, float t,
   }
 }
 
-template <int NJ, int RGM>
+template <int NJ, int RGM, int SC>
 __device__ __forceinline__ void fwd_dispatch(bool first, bool last, const Smem& sm, int Wp,
                                              int li, f4 (&y)[NJ][RGM],
-                                             f4 (&yo)[NJ][RGM]) {
+                                             f4 (&yo)[NJ][RGM], float& amax) {
   if (first && last)
-    layer_fwd<NJ, RGM, 1, 1>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo);
+    layer_fwd<NJ, RGM, 1, 1, SC>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
   else if (first)
-    layer_fwd<NJ, RGM, 1, RGM>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo);
+    layer_fwd<NJ, RGM, 1, RGM, SC>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
   else if (last)
-    layer_fwd<NJ, RGM, RGM, 1>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo);
+    layer_fwd<NJ, RGM, RGM, 1, SC>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
   else
-    layer_fwd<NJ, RGM, RGM, RGM>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo);
+    layer_fwd<NJ, RGM, RGM, RGM, SC>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
 }
 
-template <int NJ, int RGM>
+template <int NJ, int RGM, int SC>
 __device__ __forceinline__ void bwd_dispatch(bool first, bool last, const Smem& sm, int Wp,
                                              int li, int lane, f4 (&y)[NJ][RGM],
                                              const f4 (&yb)[NJ][RGM], f4 (&wb)[NJ][RGM],
-                                             float* bbar_row) {
+                                             float* bbar_row, float& amax) {
   if (first && last)
-    layer_bwd<NJ, RGM, 1, 1>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb, bbar_row);
+    layer_bwd<NJ, RGM, 1, 1, SC>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb, bbar_row,
+                                 amax);
   else if (first)
-    layer_bwd<NJ, RGM, 1, RGM>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb, bbar_row);
+    layer_bwd<NJ, RGM, 1, RGM, SC>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb,
+                                   bbar_row, amax);
   else if (last)
-    layer_bwd<NJ, RGM, RGM, 1>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb, bbar_row);
+    layer_bwd<NJ, RGM, RGM, 1, SC>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb,
+                                   bbar_row, amax);
   else
-    layer_bwd<NJ, RGM, RGM, RGM>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb,
-                                 bbar_row);
+    layer_bwd<NJ, RGM, RGM, RGM, SC>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb,
+                                     bbar_row, amax);
 }
 
 template <int NJ, int RGM>
@@ -306,7 +492,7 @@ __device__ __forceinline__ void ckpt_load(const float* __restrict__ base, int la
       y[c][g] = *reinterpret_cast<const f4*>(base + ((c * RGM + g) * 64 + lane) * 4);
 }
 
-template <int RP, int MODE, int NJ>
+template <int RP, int MODE, int NJ, int SC>
 __device__ void run_workgroup(const KNet& net, const KInst& inst, const KGrid& grid,
                               int kind, int wg, const float* __restrict__ s,
                               const float* __restrict__ mu, const Smem& sm) {
@@ -342,6 +528,7 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, const KGrid& g
   constexpr int64_t kSlot = 4 * RGM * 64 * 4;  // floats per checkpointed layer
 
   // ---- forward sweep ------------------------------------------------------
+  float amax = 0.f;  // largest |a| met by this lane (sin/cos range check)
   f4 y[NJ][RGM], yo[NJ][RGM];
   input_jets<NJ, RGM>(net, x, t, y);
   for (int l = 1; l <= L - 1; ++l) {
@@ -351,7 +538,7 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, const KGrid& g
     stage_layer(net, s, l, KI, KO, sm);
     __syncthreads();
     const int Wp = (net.M[l] + 3) & ~3;
-    fwd_dispatch<NJ, RGM>(first, last, sm, Wp, li, y, yo);
+    fwd_dispatch<NJ, RGM, SC>(first, last, sm, Wp, li, y, yo, amax);
     if constexpr (MODE == MODE_GRAD)
       if (!last) ckpt_store<NJ, RGM>(ckbase + (l - 1) * kSlot, lane, yo);
 #pragma unroll
@@ -472,7 +659,8 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, const KGrid& g
       input_jets<NJ, RGM>(net, x, t, y);
     else
       ckpt_load<NJ, RGM>(ckbase + (l - 2) * kSlot, lane, y);
-    bwd_dispatch<NJ, RGM>(first, last, sm, Wp, li, lane, y, yb, wb, sm.bbar + wave * grid.Wmax_p);
+    bwd_dispatch<NJ, RGM, SC>(first, last, sm, Wp, li, lane, y, yb, wb,
+                              sm.bbar + wave * grid.Wmax_p, amax);
     if (first)
       input_jets<NJ, RGM>(net, x, t, y);
     else
@@ -506,11 +694,22 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, const KGrid& g
       rec[4 + net.offS[l] + i] =
           ((sm.sbar[i] + sm.sbar[RP + i]) + sm.sbar[2 * RP + i]) + sm.sbar[3 * RP + i];
   }
+  if constexpr (SC == SC_TRACK) {
+    // flag the workgroup for the accurate relaunch if any lane met |a| > kFastRange
+    const bool bad = __any(!(amax <= kFastRange));
+    if (lane == 0) sm.lw[wave] = bad ? 1.f : 0.f;
+    __syncthreads();
+    if (tid == 0)
+      grid.flags[blockIdx.x] = (sm.lw[0] + sm.lw[1] + sm.lw[2] + sm.lw[3]) > 0.f ? 1 : 0;
+  }
 }
 
-template <int RP, int MODE>
+template <int RP, int MODE, int SC>
 __global__ __launch_bounds__(kThreads) void lrnr_fused_kernel(KNet net, KInst inst,
                                                               KGrid grid) {
+  if constexpr (SC == SC_ACC) {
+    if (grid.flags[blockIdx.x] == 0) return;  // only workgroups flagged by SC_TRACK
+  }
   extern __shared__ float4 smem_raw[];
   float* base = reinterpret_cast<float*>(smem_raw);
   const int Wm = grid.Wmax_p;
@@ -536,50 +735,45 @@ __global__ __launch_bounds__(kThreads) void lrnr_fused_kernel(KNet net, KInst in
   const float* s = inst.s + inst_id * grid.s_stride;
   const float* mu = inst.mu ? inst.mu + 3 * inst_id : nullptr;
   if constexpr (MODE == MODE_VALUE) {
-    run_workgroup<RP, MODE, 1>(net, inst, grid, kind, wg, s, mu, sm);
+    run_workgroup<RP, MODE, 1, SC>(net, inst, grid, kind, wg, s, mu, sm);
   } else if constexpr (MODE == MODE_JETS) {
-    run_workgroup<RP, MODE, 4>(net, inst, grid, kind, wg, s, mu, sm);
+    run_workgroup<RP, MODE, 4, SC>(net, inst, grid, kind, wg, s, mu, sm);
   } else {
     if (kind == 0)
-      run_workgroup<RP, MODE, 4>(net, inst, grid, kind, wg, s, mu, sm);
+      run_workgroup<RP, MODE, 4, SC>(net, inst, grid, kind, wg, s, mu, sm);
     else
-      run_workgroup<RP, MODE, 1>(net, inst, grid, kind, wg, s, mu, sm);
+      run_workgroup<RP, MODE, 1, SC>(net, inst, grid, kind, wg, s, mu, sm);
   }
+}
+
+template <int RP, int MODE, int SC>
+static hipError_t launch_one(const KNet& net, const KInst& inst, const KGrid& grid,
+                             hipStream_t stream) {
+  const dim3 blocks((unsigned)(grid.B * grid.G_inst)), threads(kThreads);
+  const size_t lds = fused_lds_bytes(RP, grid.Wmax_p);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)lrnr_fused_kernel<RP, MODE, SC>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((lrnr_fused_kernel<RP, MODE, SC>), blocks, threads, lds, stream, net, inst,
+                     grid);
+  return hipGetLastError();
 }
 
 template <int RP>
 hipError_t launch_rp(int mode, const KNet& net, const KInst& inst, const KGrid& grid,
-                            hipStream_t stream) {
-  const dim3 blocks((unsigned)(grid.B * grid.G_inst)), threads(kThreads);
-  const size_t lds = fused_lds_bytes(RP, grid.Wmax_p);
-  if (lds > 65536) {
-    const void* fns[4] = {(const void*)lrnr_fused_kernel<RP, MODE_JETS>,
-                          (const void*)lrnr_fused_kernel<RP, MODE_VALUE>,
-                          (const void*)lrnr_fused_kernel<RP, MODE_LOSS>,
-                          (const void*)lrnr_fused_kernel<RP, MODE_GRAD>};
-    hipError_t e = hipFuncSetAttribute(fns[mode & 3], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess) return e;
-  }
+                     hipStream_t stream) {
   switch (mode) {
-    case MODE_JETS:
-      hipLaunchKernelGGL((lrnr_fused_kernel<RP, MODE_JETS>), blocks, threads, lds, stream, net,
-                         inst, grid);
-      break;
-    case MODE_VALUE:
-      hipLaunchKernelGGL((lrnr_fused_kernel<RP, MODE_VALUE>), blocks, threads, lds, stream, net,
-                         inst, grid);
-      break;
-    case MODE_LOSS:
-      hipLaunchKernelGGL((lrnr_fused_kernel<RP, MODE_LOSS>), blocks, threads, lds, stream, net,
-                         inst, grid);
-      break;
-    default:
-      hipLaunchKernelGGL((lrnr_fused_kernel<RP, MODE_GRAD>), blocks, threads, lds, stream, net,
-                         inst, grid);
-      break;
+    case MODE_JETS: return launch_one<RP, MODE_JETS, SC_REDO>(net, inst, grid, stream);
+    case MODE_VALUE: return launch_one<RP, MODE_VALUE, SC_REDO>(net, inst, grid, stream);
+    case MODE_LOSS: return launch_one<RP, MODE_LOSS, SC_REDO>(net, inst, grid, stream);
+    default: {
+      hipError_t e = launch_one<RP, MODE_GRAD, SC_TRACK>(net, inst, grid, stream);
+      if (e != hipSuccess) return e;
+      return launch_one<RP, MODE_GRAD, SC_ACC>(net, inst, grid, stream);
+    }
   }
-  return hipGetLastError();
 }
 
 }  // namespace lrnr

@@ -58,6 +58,7 @@ struct KGrid {
   float* partials;          // [B * G_inst][P]
   float* ckpt;              // GRAD: [B * G_inst * kWaves][ckpt_per_wave]
   int64_t ckpt_per_wave;
+  int* flags;               // GRAD: [B * G_inst] workgroups that met |a| > kFastRange
 };
 
 // Record layout: [0..3) loss sums by kind, [3] unused, [4, 4 + r_total) grad s,

@@ -159,6 +159,18 @@ def test_net_shapes(M, rank):
     check_loss_grad(w, tag=f"shape {M}")
 
 
+def test_large_preactivations_take_the_accurate_path():
+    """Four neurons of layer 1 get zero U-rows and bias 2^25, so their
+    pre-activation is exactly 2^25 at every point (and the oracle exact).  The
+    fast sin/cos reduction is not valid there (its quadrant index passes
+    2^24); parity holds only if the accurate path is taken."""
+    w = custom(51, (2, 32, 32, 32, 1), 8, 600, 70, 70)
+    w.net.U[0][:4, :] = 0.0
+    w.net.b[0][:4] = np.float32(2.0 ** 25)
+    check_jets(w, tag="large |a|")
+    check_loss_grad(w, tag="large |a|")
+
+
 def test_big_net_reduced_points():
     w = wl.big_lrnr(1, 2048)
     check_jets(w, tag="big 2048")
