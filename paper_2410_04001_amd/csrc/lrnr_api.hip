@@ -118,7 +118,9 @@ Plan make_plan(const KNet& k, int RP, int Wmax_p, const lrnr_points* pts, int B,
   g.P = record_floats(k);
   g.Wmax_p = Wmax_p;
   g.s_stride = k.r_total;
-  g.ckpt_per_wave = grad ? (int64_t)(k.L - 2) * 4 * (RP / 4) * 64 * 4 : 0;
+  // (L-1) slots per 64-point tile: y^2..y^{L-1} in the forward sweep, then
+  // ybar^2..ybar^{L-1} on their way down in the reverse sweep
+  g.ckpt_per_wave = grad ? (int64_t)(k.L - 1) * 4 * (RP / 4) * 64 * 4 : 0;
   p.nchunk = (g.G_inst + kRedChunk - 1) / kRedChunk;
   size_t off = 0;
   p.off_partials = off;

@@ -134,23 +134,28 @@ __device__ __forceinline__ int sum4_component(int lane) {
 // factor entries broadcast from LDS.
 // ---------------------------------------------------------------------------
 
+// The factor entries of one group are read from LDS into registers before
+// any of its MFMAs issue, so that only the first read's latency is exposed
+// (reading them one by one between MFMA batches stalls the wave on each).
+
 // a_c = U[w0..w0+3] (s*y_c) (+ b for the value jet)
 template <int NJ, int RGM, int RGI>
 __device__ __forceinline__ void u_side(const float* __restrict__ Us, const float* __restrict__ bs,
                                        int w0, int li, const f4 (&y)[NJ][RGM], f4 (&a)[NJ]) {
   constexpr int KI = 4 * RGI;
+  const float* urow = Us + (w0 + li) * KI;
+  f4 u4[RGI];
+#pragma unroll
+  for (int g = 0; g < RGI; ++g) u4[g] = *reinterpret_cast<const f4*>(urow + 4 * g);
   a[0] = *reinterpret_cast<const f4*>(bs + w0);
 #pragma unroll
   for (int c = 1; c < NJ; ++c) a[c] = zero4();
-  const float* urow = Us + (w0 + li) * KI;
 #pragma unroll
-  for (int g = 0; g < RGI; ++g) {
-    const f4 u4 = *reinterpret_cast<const f4*>(urow + 4 * g);
+  for (int g = 0; g < RGI; ++g)
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-      for (int c = 0; c < NJ; ++c) a[c] = mfma4(u4[kk], y[c][g][kk], a[c]);
-  }
+      for (int c = 0; c < NJ; ++c) a[c] = mfma4(u4[g][kk], y[c][g][kk], a[c]);
 }
 
 // yo_c += V[w0..w0+3]^T z_c
@@ -158,16 +163,17 @@ template <int NJ, int RGM, int RGO>
 __device__ __forceinline__ void v_side(const float* __restrict__ Vs, int w0, int li,
                                        const f4 (&z)[NJ], f4 (&yo)[NJ][RGM]) {
   constexpr int KO = 4 * RGO;
+  float v[4][RGO];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const float* vrow = Vs + (w0 + j) * KO;
+  for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int g = 0; g < RGO; ++g) {
-      const float v = vrow[4 * g + li];
+    for (int g = 0; g < RGO; ++g) v[j][g] = Vs[(w0 + j) * KO + 4 * g + li];
 #pragma unroll
-      for (int c = 0; c < NJ; ++c) yo[c][g] = mfma4(v, z[c][j], yo[c][g]);
-    }
-  }
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int g = 0; g < RGO; ++g)
+#pragma unroll
+      for (int c = 0; c < NJ; ++c) yo[c][g] = mfma4(v[j][g], z[c][j], yo[c][g]);
 }
 
 // zb_c = V[w0..w0+3] yb_c
@@ -175,17 +181,18 @@ template <int NJ, int RGM, int RGO>
 __device__ __forceinline__ void v_rev(const float* __restrict__ Vs, int w0, int li,
                                       const f4 (&yb)[NJ][RGM], f4 (&zb)[NJ]) {
   constexpr int KO = 4 * RGO;
+  const float* vrow = Vs + (w0 + li) * KO;
+  f4 v4[RGO];
+#pragma unroll
+  for (int g = 0; g < RGO; ++g) v4[g] = *reinterpret_cast<const f4*>(vrow + 4 * g);
 #pragma unroll
   for (int c = 0; c < NJ; ++c) zb[c] = zero4();
-  const float* vrow = Vs + (w0 + li) * KO;
 #pragma unroll
-  for (int g = 0; g < RGO; ++g) {
-    const f4 v4 = *reinterpret_cast<const f4*>(vrow + 4 * g);
+  for (int g = 0; g < RGO; ++g)
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-      for (int c = 0; c < NJ; ++c) zb[c] = mfma4(v4[kk], yb[c][g][kk], zb[c]);
-  }
+      for (int c = 0; c < NJ; ++c) zb[c] = mfma4(v4[g][kk], yb[c][g][kk], zb[c]);
 }
 
 // wb_c += U[w0..w0+3]^T ab_c
@@ -193,16 +200,17 @@ template <int NJ, int RGM, int RGI>
 __device__ __forceinline__ void ut_side(const float* __restrict__ Us, int w0, int li,
                                         const f4 (&ab)[NJ], f4 (&wb)[NJ][RGM]) {
   constexpr int KI = 4 * RGI;
+  float u[4][RGI];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const float* ucol = Us + (w0 + j) * KI;
+  for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int g = 0; g < RGI; ++g) {
-      const float u = ucol[4 * g + li];
+    for (int g = 0; g < RGI; ++g) u[j][g] = Us[(w0 + j) * KI + 4 * g + li];
 #pragma unroll
-      for (int c = 0; c < NJ; ++c) wb[c][g] = mfma4(u, ab[c][j], wb[c][g]);
-    }
-  }
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int g = 0; g < RGI; ++g)
+#pragma unroll
+      for (int c = 0; c < NJ; ++c) wb[c][g] = mfma4(u[j][g], ab[c][j], wb[c][g]);
 }
 
 // Scheduling hint for a pipelined loop body whose first NM MFMAs do not depend
@@ -217,21 +225,69 @@ __device__ __forceinline__ void interleave() {
   }
 }
 
+// sin and cos of small arguments with the hardware v_sin_f32 / v_cos_f32,
+// which take revolutions: rev = x / (2 pi) as a two-term product
+// (1/(2 pi) = kInv2PiHi + kInv2PiLo), reduced exactly to f = rev - rint(rev)
+// in [-1/2, 1/2].  Measured on the device against FP64: absolute error below
+// 4.3e-7 for |x| <= kHwRange (1.3e-7 for |x| <= 2).
+constexpr float kHwRange = 8.0f;
+constexpr float kInv2PiHi = 0.15915493667125701904f;
+constexpr float kInv2PiLo = 6.42063824329852652e-09f;
+
+__device__ __forceinline__ void sincos_hw(float x, float& s, float& c) {
+  const float rev = __builtin_fmaf(x, kInv2PiHi, x * kInv2PiLo);
+  const float f = rev - __builtin_rintf(rev);
+  s = __builtin_amdgcn_sinf(f);
+  c = __builtin_amdgcn_cosf(f);
+}
+
+// sin/cos of the four pre-activations of a neuron group: the hardware path
+// when every lane of the wave is within kHwRange (a wave-uniform choice),
+// otherwise the Cody-Waite polynomial; ACC selects ocml's sincosf.
+template <bool ACC>
+__device__ __forceinline__ void sincos4(const f4& a, f4& sn, f4& cs, float& amax) {
+  const float m = fmaxf(fmaxf(fabsf(a[0]), fabsf(a[1])), fmaxf(fabsf(a[2]), fabsf(a[3])));
+  amax = fmaxf(amax, m);
+  if constexpr (ACC) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float s, c;
+      sincosf(a[j], &s, &c);
+      sn[j] = s;
+      cs[j] = c;
+    }
+  } else {
+    if (__all(m <= kHwRange)) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float s, c;
+        sincos_hw(a[j], s, c);
+        sn[j] = s;
+        cs[j] = c;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float s, c;
+        sincos_fast(a[j], s, c);
+        sn[j] = s;
+        cs[j] = c;
+      }
+    }
+  }
+}
+
 // z jets = sin jets of a (value, d/dx, d/dt, d2/dx2); tracks max |a_v|
 template <int NJ, bool ACC>
 __device__ __forceinline__ void sigma_fwd(const f4 (&a)[NJ], f4 (&z)[NJ], float& amax) {
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    float sn, cs;
-    sincos_sel<ACC>(a[0][j], sn, cs);
-    amax = fmaxf(amax, fabsf(a[0][j]));
-    z[0][j] = sn;
-    if constexpr (NJ == 4) {
-      const float ax = a[1][j];
-      z[1][j] = cs * ax;
-      z[2][j] = cs * a[2][j];
-      z[3][j] = cs * a[3][j] - sn * ax * ax;
-    }
+  f4 sn, cs;
+  sincos4<ACC>(a[0], sn, cs, amax);
+  z[0] = sn;
+  if constexpr (NJ == 4) {
+    const f4 ax = a[1];
+    z[1] = cs * ax;
+    z[2] = cs * a[2];
+    z[3] = cs * a[3] - sn * ax * ax;
   }
 }
 
@@ -239,21 +295,17 @@ __device__ __forceinline__ void sigma_fwd(const f4 (&a)[NJ], f4 (&z)[NJ], float&
 template <int NJ, bool ACC>
 __device__ __forceinline__ void sigma_bwd(const f4 (&a)[NJ], const f4 (&zb)[NJ], f4 (&ab)[NJ],
                                           float& amax) {
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    float sn, cs;
-    sincos_sel<ACC>(a[0][j], sn, cs);
-    amax = fmaxf(amax, fabsf(a[0][j]));
-    if constexpr (NJ == 4) {
-      const float ax = a[1][j], at = a[2][j], axx = a[3][j];
-      const float zv = zb[0][j], zx = zb[1][j], zt = zb[2][j], zxx = zb[3][j];
-      ab[3][j] = cs * zxx;
-      ab[2][j] = cs * zt;
-      ab[1][j] = cs * zx - 2.f * sn * ax * zxx;
-      ab[0][j] = cs * zv - sn * (ax * zx + at * zt + axx * zxx) - cs * ax * ax * zxx;
-    } else {
-      ab[0][j] = cs * zb[0][j];
-    }
+  f4 sn, cs;
+  sincos4<ACC>(a[0], sn, cs, amax);
+  if constexpr (NJ == 4) {
+    const f4 ax = a[1], at = a[2], axx = a[3];
+    const f4 zv = zb[0], zx = zb[1], zt = zb[2], zxx = zb[3];
+    ab[3] = cs * zxx;
+    ab[2] = cs * zt;
+    ab[1] = cs * zx - 2.f * sn * ax * zxx;
+    ab[0] = cs * zv - sn * (ax * zx + at * zt + axx * zxx) - cs * ax * ax * zxx;
+  } else {
+    ab[0] = cs * zb[0];
   }
 }
 
@@ -399,24 +451,25 @@ struct Smem {
 };
 
 // Stage layer l's U^l [Wp][KI], V^{l+1} [Wp][KO], b^l [Wp] and s^l [KI] into
-// LDS with zero padding.
+// LDS with zero padding (NT threads cooperate).
+template <int NT>
 __device__ void stage_layer(const KNet& net, const float* __restrict__ s, int l, int KI,
-                            int KO, const Smem& sm) {
+                            int KO, float* __restrict__ Us, float* __restrict__ Vs,
+                            float* __restrict__ bs, float* __restrict__ ss) {
   const int W = net.M[l], Wp = (W + 3) & ~3, rl = net.r[l], ro = net.r[l + 1];
   const float* __restrict__ U = net.U + net.offU[l];
   const float* __restrict__ V = net.V + net.offV[l + 1];
   const float* __restrict__ b = net.b + net.offB[l];
-  for (int i = threadIdx.x; i < Wp * KI; i += kThreads) {
+  for (int i = threadIdx.x; i < Wp * KI; i += NT) {
     const int w = i / KI, k = i - w * KI;
-    sm.Us[i] = (w < W && k < rl) ? U[w * rl + k] : 0.f;
+    Us[i] = (w < W && k < rl) ? U[w * rl + k] : 0.f;
   }
-  for (int i = threadIdx.x; i < Wp * KO; i += kThreads) {
+  for (int i = threadIdx.x; i < Wp * KO; i += NT) {
     const int w = i / KO, k = i - w * KO;
-    sm.Vs[i] = (w < W && k < ro) ? V[w * ro + k] : 0.f;
+    Vs[i] = (w < W && k < ro) ? V[w * ro + k] : 0.f;
   }
-  for (int i = threadIdx.x; i < Wp; i += kThreads) sm.bs[i] = i < W ? b[i] : 0.f;
-  for (int i = threadIdx.x; i < KI; i += kThreads)
-    sm.ss[i] = i < rl ? s[net.offS[l] + i] : 0.f;
+  for (int i = threadIdx.x; i < Wp; i += NT) bs[i] = i < W ? b[i] : 0.f;
+  for (int i = threadIdx.x; i < KI; i += NT) ss[i] = i < rl ? s[net.offS[l] + i] : 0.f;
 }
 
 // Jets of y^1 = V^1T (x, t): value V^1T (x,t), d/dx row 0 of V^1, d/dt row 1,
@@ -535,7 +588,7 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, const KGrid& g
     const bool first = l == 1, last = l == L - 1;
     const int KI = first ? 4 : RP, KO = last ? 4 : RP;
     __syncthreads();
-    stage_layer(net, s, l, KI, KO, sm);
+    stage_layer<kThreads>(net, s, l, KI, KO, sm.Us, sm.Vs, sm.bs, sm.ss);
     __syncthreads();
     const int Wp = (net.M[l] + 3) & ~3;
     fwd_dispatch<NJ, RGM, SC>(first, last, sm, Wp, li, y, yo, amax);
@@ -653,7 +706,7 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, const KGrid& g
         rec[4 + net.r_total + net.offB[L]] = v;
       }
     }
-    stage_layer(net, s, l, KI, KO, sm);
+    stage_layer<kThreads>(net, s, l, KI, KO, sm.Us, sm.Vs, sm.bs, sm.ss);
     __syncthreads();
     if (first)
       input_jets<NJ, RGM>(net, x, t, y);
@@ -759,21 +812,6 @@ static hipError_t launch_one(const KNet& net, const KInst& inst, const KGrid& gr
   hipLaunchKernelGGL((lrnr_fused_kernel<RP, MODE, SC>), blocks, threads, lds, stream, net, inst,
                      grid);
   return hipGetLastError();
-}
-
-template <int RP>
-hipError_t launch_rp(int mode, const KNet& net, const KInst& inst, const KGrid& grid,
-                     hipStream_t stream) {
-  switch (mode) {
-    case MODE_JETS: return launch_one<RP, MODE_JETS, SC_REDO>(net, inst, grid, stream);
-    case MODE_VALUE: return launch_one<RP, MODE_VALUE, SC_REDO>(net, inst, grid, stream);
-    case MODE_LOSS: return launch_one<RP, MODE_LOSS, SC_REDO>(net, inst, grid, stream);
-    default: {
-      hipError_t e = launch_one<RP, MODE_GRAD, SC_TRACK>(net, inst, grid, stream);
-      if (e != hipSuccess) return e;
-      return launch_one<RP, MODE_GRAD, SC_ACC>(net, inst, grid, stream);
-    }
-  }
 }
 
 }  // namespace lrnr

@@ -1,5 +1,5 @@
 // Instantiation of the fused kernel for rank tile 20.
-#include "lrnr_fused_impl.h"
+#include "lrnr_fused_ws.h"
 
 namespace lrnr {
 template hipError_t launch_rp<20>(int, const KNet&, const KInst&, const KGrid&, hipStream_t);
