@@ -162,6 +162,66 @@ int32_t lrnr_grad_s_batched(const lrnr_net* net, int32_t B, const float* s,
                             void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Task tables: one launch over many independent instances (the batched
+ * differentiation and serving forms built around the method of Sections 2-3).
+ * Each task has its own net (an index into nets[]), coefficients, PDE
+ * parameters, points and outputs.  The device work runs on a persistent grid
+ * that strides over 256-point tiles of all tasks; every task's reduction
+ * runs in a fixed order over its own tiles only, so a task's results are
+ * bitwise identical whatever other tasks share the launch, and equal those of
+ * the single-instance entry points up to the order of FP32 operations.
+ *
+ * Modes:
+ *  LRNR_MODE_JETS  out [4][n_r] = u, u_x, u_t, u_xx at pts.xt_r (as lrnr_forward_jets)
+ *  LRNR_MODE_VALUE out [n_r]    = u at pts.xt_r (grid evaluation)
+ *  LRNR_MODE_LOSS  loss [4] of eq. 3.5-3.7 with eq. 4.1 (as lrnr_residual_loss)
+ *  LRNR_MODE_GRAD  loss [4] (nullable), grad_s [r_total], grad_b (nullable)
+ *                  (as lrnr_grad_s)
+ *  LRNR_MODE_VJP   grad_s [r_total] (and grad_b, nullable) of the scalar
+ *                  sum_c sum_i cot[c][i] * jet_c(x_i), i.e. the vector-Jacobian
+ *                  product of the forward jets with a caller cotangent.
+ * JETS, VALUE and VJP read pts.xt_r and pts.n_r only.
+ */
+#define LRNR_MODE_JETS 0
+#define LRNR_MODE_VALUE 1
+#define LRNR_MODE_LOSS 2
+#define LRNR_MODE_GRAD 3
+#define LRNR_MODE_VJP 4
+
+typedef struct lrnr_task {
+  int32_t net;          /* index into nets[]                                        */
+  int32_t reserved;     /* 0                                                        */
+  const float* s;       /* [dev] [r_total] coefficients                             */
+  const float* mu;      /* [dev] [3] (beta, nu, rho); LOSS and GRAD                 */
+  lrnr_points pts;      /* [dev] points                                              */
+  const float* s_ref;   /* [dev] [r_total] locality reference; NULL: cfg->s_ref     */
+  const float* cot;     /* [dev] [4][n_r] cotangent of (u, u_x, u_t, u_xx); VJP    */
+  float* out;           /* [dev] JETS [4][n_r], VALUE [n_r]                         */
+  float* grad_s;        /* [dev] [r_total]; GRAD and VJP                            */
+  float* grad_b;        /* [dev] [b_total] or NULL; GRAD and VJP                    */
+  float* loss;          /* [dev] [4]; LOSS (required), GRAD (nullable)              */
+} lrnr_task;
+
+/*
+ * Workspace bytes for lrnr_tasks_run with these nets and tasks (0 when the
+ * arguments are invalid).  The size depends on the nets, point counts and
+ * mode only, never on the device.
+ */
+size_t lrnr_tasks_workspace_size(int32_t mode, const lrnr_net* nets, int32_t n_nets,
+                                 const lrnr_task* tasks, int32_t n_tasks);
+
+/*
+ * Runs one mode over n_tasks tasks (n_tasks >= 1; host arrays nets[] and
+ * tasks[] are read before the call returns).  cfg (form, weights, lambda_loc)
+ * applies to every task of LOSS and GRAD; it may be NULL for the other modes.
+ * ws [dev]: at least lrnr_tasks_workspace_size() bytes, 256-B aligned.  Every
+ * net of one call is run with the rank tile of the largest rank among them.
+ */
+int32_t lrnr_tasks_run(int32_t mode, const lrnr_net* nets, int32_t n_nets,
+                       const lrnr_task* tasks, int32_t n_tasks, const lrnr_loss_cfg* cfg,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/*
  * FastLRNR construction (Section 2.2, eq. 2.7; construction of Section 4):
  * snapshots of the hidden states z^l at n_snap points for each of the n_s
  * coefficient vectors, POD basis Xi^l (leading r_hat[l] left singular vectors,

@@ -239,6 +239,19 @@ def lrnr_forward_jets(net, s_list, xt):
     return np.stack([jets[c] for c in JETS])
 
 
+def lrnr_jets_vjp(net, s_list, xt, cot):
+    """Vector-Jacobian product of the forward jets: the gradients w.r.t. s
+    (flat) and b (flat) of sum_i sum_c cot[c][i] * jet_c(x_i), with cot [4][n]
+    in the order u, u_x, u_t, u_xx (chain rule through eq. 2.1-2.2)."""
+    W = dense_weights(net.U, s_list, net.V)
+    jets, cache = mlp_forward(W, net.b, xt)
+    cot = _f(np.asarray(cot))
+    ubar = {c: cot[k] for k, c in enumerate(JETS)}
+    gW, gb = mlp_backward(W, cache, ubar)
+    gs = grad_s_from_dense(gW, net.U, net.V)
+    return np.concatenate(gs), np.concatenate(gb)
+
+
 def lrnr_hidden_values(net, s_list, xt):
     """Post-activation hidden states z^l (values only) at the points: list of
     [n][M_l] for l = 1..L-1 (snapshot data of eq. 2.7)."""

@@ -46,9 +46,23 @@ class LrnrLossCfg(C.Structure):
     ]
 
 
+MODE_JETS, MODE_VALUE, MODE_LOSS, MODE_GRAD, MODE_VJP = 0, 1, 2, 3, 4
+
+
+class LrnrTask(C.Structure):
+    _fields_ = [
+        ("net", C.c_int32), ("reserved", C.c_int32),
+        ("s", C.c_void_p), ("mu", C.c_void_p),
+        ("pts", LrnrPoints),
+        ("s_ref", C.c_void_p), ("cot", C.c_void_p), ("out", C.c_void_p),
+        ("grad_s", C.c_void_p), ("grad_b", C.c_void_p), ("loss", C.c_void_p),
+    ]
+
+
 P = C.c_void_p
 I32, I64, F32, SZ = C.c_int32, C.c_int64, C.c_float, C.c_size_t
 NETP, PTSP, CFGP = C.POINTER(LrnrNet), C.POINTER(LrnrPoints), C.POINTER(LrnrLossCfg)
+TASKP = C.POINTER(LrnrTask)
 
 # name -> (restype, argtypes); the exported surface of include/lrnr.h
 SIGNATURES = {
@@ -58,6 +72,8 @@ SIGNATURES = {
     "lrnr_residual_loss": (I32, [NETP, P, P, PTSP, CFGP, P, P, SZ, P]),
     "lrnr_grad_s": (I32, [NETP, P, P, PTSP, CFGP, P, P, P, P, SZ, P]),
     "lrnr_grad_s_batched": (I32, [NETP, I32, P, P, PTSP, CFGP, P, P, P, SZ, P]),
+    "lrnr_tasks_workspace_size": (SZ, [I32, NETP, I32, TASKP, I32]),
+    "lrnr_tasks_run": (I32, [I32, NETP, I32, TASKP, I32, CFGP, P, SZ, P]),
     "fastlrnr_build": (I32, [NETP, P, I32, P, I64, C.POINTER(I32), C.POINTER(P), P]),
     "fastlrnr_get_net": (I32, [P, NETP]),
     "fastlrnr_get_indices": (I32, [P, C.POINTER(I32)]),

@@ -183,6 +183,79 @@ def grad_s_batched(net, s, mu, pts, cfg, ws=None):
     return gs, loss
 
 
+MODE_JETS, MODE_VALUE, MODE_LOSS, MODE_GRAD, MODE_VJP = (
+    cl.MODE_JETS, cl.MODE_VALUE, cl.MODE_LOSS, cl.MODE_GRAD, cl.MODE_VJP)
+
+
+class TaskTable:
+    """Host description of a task table for lrnr_tasks_run.
+
+    Each task references device memory by address; the table keeps the tensors
+    it was given alive.  Build it once and run it many times while those
+    tensors keep their storage (in-place updates of s are seen by every run).
+    """
+
+    def __init__(self, nets):
+        self.nets = list(nets)
+        self._nets_c = (cl.LrnrNet * len(self.nets))(*[n._c for n in self.nets])
+        self._tasks = []
+        self._keep = []
+        self._arr = None
+
+    def add(self, net=0, s=None, mu=None, xt_r=None, x_0=None, t_b=None, s_ref=None,
+            cot=None, out=None, grad_s=None, grad_b=None, loss=None):
+        """Each argument is a contiguous float32 device tensor or None; a row
+        view of a larger tensor (s[i], xt[i]) addresses that row."""
+        def ref(x):
+            if x is None:
+                return None
+            if x.dtype != torch.float32 or not x.is_contiguous():
+                raise ValueError("task arrays must be contiguous float32 tensors")
+            self._keep.append(x)
+            return x.data_ptr()
+
+        def cnt(x, per):
+            return 0 if x is None else x.numel() // per
+
+        t = cl.LrnrTask()
+        t.net = int(net)
+        t.s = ref(s)
+        t.mu = ref(mu)
+        t.pts = cl.LrnrPoints(ref(xt_r), cnt(xt_r, 2), ref(x_0), cnt(x_0, 1),
+                              ref(t_b), cnt(t_b, 1))
+        t.s_ref = ref(s_ref)
+        t.cot = ref(cot)
+        t.out = ref(out)
+        t.grad_s = ref(grad_s)
+        t.grad_b = ref(grad_b)
+        t.loss = ref(loss)
+        self._tasks.append(t)
+        self._arr = None
+        return len(self._tasks) - 1
+
+    def __len__(self):
+        return len(self._tasks)
+
+    def _c(self):
+        if self._arr is None:
+            self._arr = (cl.LrnrTask * len(self._tasks))(*self._tasks)
+        return self._arr
+
+    def workspace_size(self, mode):
+        n = cl.lib().lrnr_tasks_workspace_size(int(mode), self._nets_c, len(self.nets),
+                                               self._c(), len(self._tasks))
+        if n == 0:
+            raise cl.LrnrError(cl.EINVAL, "lrnr_tasks_workspace_size")
+        return n
+
+    def run(self, mode, cfg=None, ws=None, device="cuda"):
+        ws = ws or _ws(device)
+        wp, wn = ws.ptr_size(self.workspace_size(mode))
+        cl.check(cl.lib().lrnr_tasks_run(int(mode), self._nets_c, len(self.nets), self._c(),
+                                         len(self._tasks), None if cfg is None else cfg.c(),
+                                         wp, wn, _stream()), "lrnr_tasks_run")
+
+
 class HipEvent:
     """A timing hipEvent_t made through the HIP runtime (torch's Event will
     not report the time of an event recorded outside torch)."""

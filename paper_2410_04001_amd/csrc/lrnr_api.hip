@@ -12,9 +12,11 @@
 using namespace lrnr;
 
 namespace {
-
 thread_local std::string g_detail;
 thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+}  // namespace
+
+namespace lrnr {
 
 int32_t fail(int32_t code, const char* fmt, ...) {
   char buf[512];
@@ -90,16 +92,20 @@ int32_t check_points(const lrnr_points* pts) {
   return LRNR_OK;
 }
 
-int32_t check_cfg(const lrnr_loss_cfg* cfg) {
+int32_t check_cfg(const lrnr_loss_cfg* cfg, bool sref_elsewhere) {
   if (!cfg) return fail(LRNR_EINVAL, "loss cfg is NULL");
   if (cfg->form != 0 && cfg->form != 1) return fail(LRNR_EINVAL, "form=%d, expected 0 or 1", cfg->form);
   if (!std::isfinite(cfg->w_r) || !std::isfinite(cfg->w_0) || !std::isfinite(cfg->w_b) ||
       !std::isfinite(cfg->lambda_loc))
     return fail(LRNR_EINVAL, "non-finite loss weight");
-  if (cfg->lambda_loc != 0.f && !cfg->s_ref)
+  if (cfg->lambda_loc != 0.f && !cfg->s_ref && !sref_elsewhere)
     return fail(LRNR_EINVAL, "lambda_loc != 0 needs s_ref");
   return LRNR_OK;
 }
+
+}  // namespace lrnr
+
+namespace {
 
 struct Plan {
   KGrid grid;
@@ -180,10 +186,10 @@ int32_t run_loss(const lrnr_net* net, int B, const float* s, const float* mu,
   hipStream_t hs = static_cast<hipStream_t>(stream);
   if (p.grid.G_inst > 0) {
     const bool timed = g_ev_start && g_ev_stop;
-    if (timed) hipEventRecord(g_ev_start, hs);
+    if (timed) (void)hipEventRecord(g_ev_start, hs);
     hipError_t e = launch_fused(RP, grad ? MODE_GRAD : MODE_LOSS, k, in, p.grid, hs);
     if (timed) {
-      hipEventRecord(g_ev_stop, hs);
+      (void)hipEventRecord(g_ev_stop, hs);
       g_ev_start = g_ev_stop = nullptr;
     }
     if (e != hipSuccess) return hip_fail(e, "fused kernel launch");

@@ -7,6 +7,10 @@ namespace lrnr {
 template <int RP>
 hipError_t launch_rp(int mode, const KNet& net, const KInst& inst, const KGrid& grid,
                      hipStream_t stream);
+template <int RP>
+hipError_t launch_table_rp(int mode, const KTableGrid& tg, int grid, hipStream_t stream);
+template <int RP>
+int table_grid_rp(int mode, int Wmax_p);
 
 size_t fused_lds_bytes(int RP, int Wmax_p) {
   const size_t floats = (size_t)Wmax_p * RP * 2 + Wmax_p + RP + (size_t)kWaves * Wmax_p +
@@ -34,6 +38,30 @@ hipError_t launch_fused(int RP, int mode, const KNet& net, const KInst& inst,
     case 24: return launch_rp<24>(mode, net, inst, grid, stream);
     case 32: return launch_rp<32>(mode, net, inst, grid, stream);
     default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_table(int RP, int mode, const KTableGrid& tg, int grid, hipStream_t stream) {
+  switch (RP) {
+    case 4: return launch_table_rp<4>(mode, tg, grid, stream);
+    case 8: return launch_table_rp<8>(mode, tg, grid, stream);
+    case 16: return launch_table_rp<16>(mode, tg, grid, stream);
+    case 20: return launch_table_rp<20>(mode, tg, grid, stream);
+    case 24: return launch_table_rp<24>(mode, tg, grid, stream);
+    case 32: return launch_table_rp<32>(mode, tg, grid, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int table_grid_size(int RP, int mode, int Wmax_p) {
+  switch (RP) {
+    case 4: return table_grid_rp<4>(mode, Wmax_p);
+    case 8: return table_grid_rp<8>(mode, Wmax_p);
+    case 16: return table_grid_rp<16>(mode, Wmax_p);
+    case 20: return table_grid_rp<20>(mode, Wmax_p);
+    case 24: return table_grid_rp<24>(mode, Wmax_p);
+    case 32: return table_grid_rp<32>(mode, Wmax_p);
+    default: return -1;
   }
 }
 

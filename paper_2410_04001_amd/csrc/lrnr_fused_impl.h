@@ -546,9 +546,11 @@ __device__ __forceinline__ void ckpt_load(const float* __restrict__ base, int la
 }
 
 template <int RP, int MODE, int NJ, int SC>
-__device__ void run_workgroup(const KNet& net, const KInst& inst, const KGrid& grid,
-                              int kind, int wg, const float* __restrict__ s,
-                              const float* __restrict__ mu, const Smem& sm) {
+__device__ void run_workgroup(const KNet& net, const KInst& inst, int64_t ckpt_per_wave,
+                              int Wmax_p, const KTile& tile, int kind, int wg,
+                              const float* __restrict__ s, const float* __restrict__ mu,
+                              const Smem& sm) {
+  constexpr bool REV = reverse_mode(MODE);
   constexpr int RGM = RP / 4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 3;
   const int L = net.L;
@@ -576,8 +578,7 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, const KGrid& g
   }
 
   float* ckbase = nullptr;
-  if constexpr (MODE == MODE_GRAD)
-    ckbase = grid.ckpt + ((int64_t)blockIdx.x * kWaves + wave) * grid.ckpt_per_wave;
+  if constexpr (REV) ckbase = tile.ck + wave * ckpt_per_wave;
   constexpr int64_t kSlot = 4 * RGM * 64 * 4;  // floats per checkpointed layer
 
   // ---- forward sweep ------------------------------------------------------
@@ -592,7 +593,7 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, const KGrid& g
     __syncthreads();
     const int Wp = (net.M[l] + 3) & ~3;
     fwd_dispatch<NJ, RGM, SC>(first, last, sm, Wp, li, y, yo, amax);
-    if constexpr (MODE == MODE_GRAD)
+    if constexpr (REV)
       if (!last) ckpt_store<NJ, RGM>(ckbase + (l - 1) * kSlot, lane, yo);
 #pragma unroll
     for (int c = 0; c < NJ; ++c)
@@ -629,7 +630,14 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, const KGrid& g
   float ub[NJ];
 #pragma unroll
   for (int c = 0; c < NJ; ++c) ub[c] = 0.f;
-  if constexpr (NJ == 4) {
+  if constexpr (MODE == MODE_VJP) {
+    // cotangent of the jets supplied by the caller (interior points only)
+    if (valid) {
+      const int64_t n = inst.n_r;
+#pragma unroll
+      for (int c = 0; c < NJ; ++c) ub[c] = inst.cot[c * n + p];
+    }
+  } else if constexpr (NJ == 4) {
     const float beta = mu[0], nu = mu[1], rho = mu[2];
     const float res = u[2] + beta * u[1] - nu * u[3] - rho * u[0] * (1.f - u[0]);
     const float phi = form == 0 ? res * res : fabsf(res);
@@ -656,7 +664,7 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, const KGrid& g
     ub[0] = valid ? (right ? -inst.wb_n : inst.wb_n) * dphi : 0.f;
   }
 
-  float* rec = grid.partials + (int64_t)blockIdx.x * grid.P;
+  float* rec = tile.rec;
   const int comp = sum4_component(lane);
 
   if constexpr (MODE == MODE_LOSS) {
@@ -713,7 +721,7 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, const KGrid& g
     else
       ckpt_load<NJ, RGM>(ckbase + (l - 2) * kSlot, lane, y);
     bwd_dispatch<NJ, RGM, SC>(first, last, sm, Wp, li, lane, y, yb, wb,
-                              sm.bbar + wave * grid.Wmax_p, amax);
+                              sm.bbar + wave * Wmax_p, amax);
     if (first)
       input_jets<NJ, RGM>(net, x, t, y);
     else
@@ -739,7 +747,7 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, const KGrid& g
     }
     __syncthreads();
     // the layer's s and b gradients, waves summed in a fixed order
-    const int W = net.M[l], rl = net.r[l], Wm = grid.Wmax_p;
+    const int W = net.M[l], rl = net.r[l], Wm = Wmax_p;
     for (int i = tid; i < W; i += kThreads)
       rec[4 + net.r_total + net.offB[l] + i] =
           ((sm.bbar[i] + sm.bbar[Wm + i]) + sm.bbar[2 * Wm + i]) + sm.bbar[3 * Wm + i];
@@ -752,8 +760,28 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, const KGrid& g
     const bool bad = __any(!(amax <= kFastRange));
     if (lane == 0) sm.lw[wave] = bad ? 1.f : 0.f;
     __syncthreads();
-    if (tid == 0)
-      grid.flags[blockIdx.x] = (sm.lw[0] + sm.lw[1] + sm.lw[2] + sm.lw[3]) > 0.f ? 1 : 0;
+    if (tid == 0) *tile.flag = (sm.lw[0] + sm.lw[1] + sm.lw[2] + sm.lw[3]) > 0.f ? 1 : 0;
+  }
+}
+
+// Dispatch on the point kind: interior points carry four jets, IC/BC points
+// (and plain value evaluation) one.
+template <int RP, int MODE, int SC>
+__device__ __forceinline__ void run_kind(const KNet& net, const KInst& inst,
+                                         int64_t ckpt_per_wave, int Wmax_p, const KTile& tile,
+                                         int kind, int wg, const float* __restrict__ s,
+                                         const float* __restrict__ mu, const Smem& sm) {
+  if constexpr (MODE == MODE_VALUE) {
+    run_workgroup<RP, MODE, 1, SC>(net, inst, ckpt_per_wave, Wmax_p, tile, kind, wg, s, mu, sm);
+  } else if constexpr (MODE == MODE_JETS || MODE == MODE_VJP) {
+    run_workgroup<RP, MODE, 4, SC>(net, inst, ckpt_per_wave, Wmax_p, tile, kind, wg, s, mu, sm);
+  } else {
+    if (kind == 0)
+      run_workgroup<RP, MODE, 4, SC>(net, inst, ckpt_per_wave, Wmax_p, tile, kind, wg, s, mu,
+                                     sm);
+    else
+      run_workgroup<RP, MODE, 1, SC>(net, inst, ckpt_per_wave, Wmax_p, tile, kind, wg, s, mu,
+                                     sm);
   }
 }
 
@@ -787,16 +815,11 @@ __global__ __launch_bounds__(kThreads) void lrnr_fused_kernel(KNet net, KInst in
   }
   const float* s = inst.s + inst_id * grid.s_stride;
   const float* mu = inst.mu ? inst.mu + 3 * inst_id : nullptr;
-  if constexpr (MODE == MODE_VALUE) {
-    run_workgroup<RP, MODE, 1, SC>(net, inst, grid, kind, wg, s, mu, sm);
-  } else if constexpr (MODE == MODE_JETS) {
-    run_workgroup<RP, MODE, 4, SC>(net, inst, grid, kind, wg, s, mu, sm);
-  } else {
-    if (kind == 0)
-      run_workgroup<RP, MODE, 4, SC>(net, inst, grid, kind, wg, s, mu, sm);
-    else
-      run_workgroup<RP, MODE, 1, SC>(net, inst, grid, kind, wg, s, mu, sm);
-  }
+  KTile tile;
+  tile.rec = grid.partials + (int64_t)blockIdx.x * grid.P;
+  tile.ck = grid.ckpt ? grid.ckpt + (int64_t)blockIdx.x * kWaves * grid.ckpt_per_wave : nullptr;
+  tile.flag = grid.flags ? grid.flags + blockIdx.x : nullptr;
+  run_kind<RP, MODE, SC>(net, inst, grid.ckpt_per_wave, grid.Wmax_p, tile, kind, wg, s, mu, sm);
 }
 
 template <int RP, int MODE, int SC>

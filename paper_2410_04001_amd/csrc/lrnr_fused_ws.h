@@ -26,6 +26,8 @@
 // after the next barrier.
 #pragma once
 
+#include <algorithm>
+
 #include "lrnr_fused_impl.h"
 
 namespace lrnr {
@@ -165,10 +167,10 @@ __device__ __forceinline__ void ws_bwd_E(const SmemWS& sm, const float* xb, int 
 // ---------------------------------------------------------------------------
 // Workgroup driver (MODE_GRAD, fast sin/cos with range tracking)
 // ---------------------------------------------------------------------------
-template <int RP, int NJ>
-__device__ void ws_run(const KNet& net, const KInst& inst, const KGrid& grid, int kind, int wg,
-                       const float* __restrict__ s, const float* __restrict__ mu,
-                       const SmemWS& sm) {
+template <int RP, int NJ, bool VJP>
+__device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave, int Wmax_p,
+                       const KTile& tile, int kind, int wg, const float* __restrict__ s,
+                       const float* __restrict__ mu, const SmemWS& sm) {
   constexpr int RGM = RP / 4;
   constexpr int64_t kSlot = 4 * RGM * 64 * 4;  // floats per checkpoint slot
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 3;
@@ -197,7 +199,7 @@ __device__ void ws_run(const KNet& net, const KInst& inst, const KGrid& grid, in
     x = (lane & 1) ? LRNR_TWO_PI_F : 0.f;
     if (valid) t = inst.t_b[p];
   }
-  float* ckbase = grid.ckpt + ((int64_t)blockIdx.x * 4 + pair) * grid.ckpt_per_wave;
+  float* ckbase = tile.ck + pair * ckpt_per_wave;
   float* xb = sm.xbuf + pair * 2 * kSlotFloats;
   float amax = 0.f;
 
@@ -244,7 +246,14 @@ __device__ void ws_run(const KNet& net, const KInst& inst, const KGrid& grid, in
     float ub[NJ];
 #pragma unroll
     for (int c = 0; c < NJ; ++c) ub[c] = 0.f;
-    if constexpr (NJ == 4) {
+    if constexpr (VJP) {
+      // cotangent of the jets supplied by the caller (interior points only)
+      if (valid) {
+        const int64_t n = inst.n_r;
+#pragma unroll
+        for (int c = 0; c < NJ; ++c) ub[c] = inst.cot[c * n + p];
+      }
+    } else if constexpr (NJ == 4) {
       const float beta = mu[0], nu = mu[1], rho = mu[2];
       const float res = u[2] + beta * u[1] - nu * u[3] - rho * u[0] * (1.f - u[0]);
       const float phi = form == 0 ? res * res : fabsf(res);
@@ -283,7 +292,7 @@ __device__ void ws_run(const KNet& net, const KInst& inst, const KGrid& grid, in
   __syncthreads();
 
   // ---- reverse sweep --------------------------------------------------------
-  float* rec = grid.partials + (int64_t)blockIdx.x * grid.P;
+  float* rec = tile.rec;
   f4 yb[NJ][RGM];  // M: ybar^{l+1};  E: wbar of the current layer
   if (isM) {
 #pragma unroll
@@ -332,7 +341,7 @@ __device__ void ws_run(const KNet& net, const KInst& inst, const KGrid& grid, in
       else
         ws_bwd_M<NJ, RGM, RGM, RGM>(sm, xb, G, li, lane, ys, yb);
     } else {
-      float* brow = sm.bbar + pair * grid.Wmax_p;
+      float* brow = sm.bbar + pair * Wmax_p;
       if (first)
         ws_bwd_E<NJ, RGM, 1>(sm, xb, G, li, lane, yb, brow, amax);
       else
@@ -366,7 +375,7 @@ __device__ void ws_run(const KNet& net, const KInst& inst, const KGrid& grid, in
       }
     }
     __syncthreads();
-    const int W = net.M[l], rl = net.r[l], Wm = grid.Wmax_p;
+    const int W = net.M[l], rl = net.r[l], Wm = Wmax_p;
     for (int i = tid; i < W; i += kWsThreads)
       rec[4 + net.r_total + net.offB[l] + i] =
           ((sm.bbar[i] + sm.bbar[Wm + i]) + sm.bbar[2 * Wm + i]) + sm.bbar[3 * Wm + i];
@@ -382,16 +391,12 @@ __device__ void ws_run(const KNet& net, const KInst& inst, const KGrid& grid, in
   if (tid == 0) {
     float any = 0.f;
     for (int w = 0; w < kWsWaves; ++w) any += sm.lw[w];
-    grid.flags[blockIdx.x] = any > 0.f ? 1 : 0;
+    *tile.flag = any > 0.f ? 1 : 0;
   }
 }
 
-template <int RP>
-__global__ __launch_bounds__(kWsThreads) void lrnr_grad_ws_kernel(KNet net, KInst inst,
-                                                                  KGrid grid) {
-  extern __shared__ float4 smem_raw[];
-  float* base = reinterpret_cast<float*>(smem_raw);
-  const int Wm = grid.Wmax_p;
+// LDS carve-up of the wave-specialised kernels.
+__device__ __forceinline__ SmemWS ws_smem(float* base, int Wm, int RP) {
   SmemWS sm;
   sm.Us = base;
   sm.Vs = sm.Us + Wm * RP;
@@ -401,6 +406,14 @@ __global__ __launch_bounds__(kWsThreads) void lrnr_grad_ws_kernel(KNet net, KIns
   sm.bbar = sm.xbuf + 4 * 2 * kSlotFloats;
   sm.sbar = sm.bbar + 4 * Wm;
   sm.lw = sm.sbar + 4 * RP;
+  return sm;
+}
+
+template <int RP>
+__global__ __launch_bounds__(kWsThreads) void lrnr_grad_ws_kernel(KNet net, KInst inst,
+                                                                  KGrid grid) {
+  extern __shared__ float4 smem_raw[];
+  const SmemWS sm = ws_smem(reinterpret_cast<float*>(smem_raw), grid.Wmax_p, RP);
 
   const int inst_id = blockIdx.x / grid.G_inst;
   int wg = blockIdx.x - inst_id * grid.G_inst;
@@ -414,10 +427,14 @@ __global__ __launch_bounds__(kWsThreads) void lrnr_grad_ws_kernel(KNet net, KIns
   }
   const float* s = inst.s + inst_id * grid.s_stride;
   const float* mu = inst.mu ? inst.mu + 3 * inst_id : nullptr;
+  KTile tile;
+  tile.rec = grid.partials + (int64_t)blockIdx.x * grid.P;
+  tile.ck = grid.ckpt + (int64_t)blockIdx.x * kWaves * grid.ckpt_per_wave;
+  tile.flag = grid.flags + blockIdx.x;
   if (kind == 0)
-    ws_run<RP, 4>(net, inst, grid, kind, wg, s, mu, sm);
+    ws_run<RP, 4, false>(net, inst, grid.ckpt_per_wave, grid.Wmax_p, tile, kind, wg, s, mu, sm);
   else
-    ws_run<RP, 1>(net, inst, grid, kind, wg, s, mu, sm);
+    ws_run<RP, 1, false>(net, inst, grid.ckpt_per_wave, grid.Wmax_p, tile, kind, wg, s, mu, sm);
 }
 
 template <int RP>
@@ -435,6 +452,188 @@ hipError_t launch_grad_ws(const KNet& net, const KInst& inst, const KGrid& grid,
   if (e != hipSuccess) return e;
   // workgroups that met |a| > kFastRange are recomputed with ocml's sin/cos
   return launch_one<RP, MODE_GRAD, SC_ACC>(net, inst, grid, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Task-table launches: a persistent grid strides over the tiles of all tasks.
+// ---------------------------------------------------------------------------
+
+// The task owning a tile: the largest t with start[t] <= tile (start is
+// non-decreasing, so the ballot of start[i] <= tile is a prefix of the lanes).
+__device__ __forceinline__ int find_task(const int* __restrict__ start, int n_tasks, int tile) {
+  const int lane = threadIdx.x & 63;
+  int t = 0;
+  for (int c = 0; c < n_tasks; c += 64) {
+    const int i = c + lane;
+    const bool le = i < n_tasks && start[i] <= tile;
+    const int cnt = __popcll(__ballot(le));
+    if (cnt > 0) t = c + cnt - 1;
+    if (cnt < 64) break;
+  }
+  return __builtin_amdgcn_readfirstlane(t);
+}
+
+struct TileRef {
+  const KTask* task;
+  int kind, wg, local;
+};
+
+__device__ __forceinline__ TileRef decode_tile(const KTableGrid& tg, int n_tasks, int tile) {
+  const int* start = reinterpret_cast<const int*>(tg.table + sizeof(KTableHdr));
+  const int t = find_task(start, n_tasks, tile);
+  TileRef r;
+  r.task = reinterpret_cast<const KTask*>(tg.table + tg.off_tasks) + t;
+  r.local = tile - start[t];
+  r.wg = r.local;
+  r.kind = 0;
+  const int Gr = r.task->G_r, G0 = r.task->G_0;
+  if (r.wg >= Gr + G0) {
+    r.kind = 2;
+    r.wg -= Gr + G0;
+  } else if (r.wg >= Gr) {
+    r.kind = 1;
+    r.wg -= Gr;
+  }
+  return r;
+}
+
+// A task whose Adam counter reached its limit is finished: its tiles are skipped.
+__device__ __forceinline__ bool task_finished(const KTask* T) {
+  return T->step != nullptr && T->steps_max > 0 && *T->step >= T->steps_max;
+}
+
+template <int RP, bool VJP>
+__global__ __launch_bounds__(kWsThreads) void lrnr_grad_ws_table_kernel(KTableGrid tg) {
+  extern __shared__ float4 smem_raw[];
+  const SmemWS sm = ws_smem(reinterpret_cast<float*>(smem_raw), tg.Wmax_p, RP);
+  const KTableHdr* hdr = reinterpret_cast<const KTableHdr*>(tg.table);
+  const int n_tasks = hdr->n_tasks, n_tiles = hdr->n_tiles;
+  float* ck = tg.ckpt + (int64_t)blockIdx.x * kWaves * tg.ckpt_per_wave;
+  for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const TileRef r = decode_tile(tg, n_tasks, tile);
+    const KTask* T = r.task;
+    if (task_finished(T)) continue;
+    KTile kt;
+    kt.rec = tg.partials + T->rec0 + (int64_t)r.local * T->P;
+    kt.ck = ck;
+    kt.flag = tg.flags + tile;
+    if (r.kind == 0)
+      ws_run<RP, 4, VJP>(T->net, T->inst, tg.ckpt_per_wave, tg.Wmax_p, kt, 0, r.wg, T->inst.s,
+                         T->inst.mu, sm);
+    else if constexpr (!VJP)
+      ws_run<RP, 1, false>(T->net, T->inst, tg.ckpt_per_wave, tg.Wmax_p, kt, r.kind, r.wg,
+                           T->inst.s, T->inst.mu, sm);
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ Smem fused_smem(float* base, int Wm, int RP) {
+  Smem sm;
+  sm.Us = base;
+  sm.Vs = sm.Us + Wm * RP;
+  sm.bs = sm.Vs + Wm * RP;
+  sm.ss = sm.bs + Wm;
+  sm.bbar = sm.ss + RP;
+  sm.sbar = sm.bbar + kWaves * Wm;
+  sm.lw = sm.sbar + kWaves * RP;
+  return sm;
+}
+
+template <int RP, int MODE, int SC>
+__global__ __launch_bounds__(kThreads) void lrnr_table_kernel(KTableGrid tg) {
+  extern __shared__ float4 smem_raw[];
+  const Smem sm = fused_smem(reinterpret_cast<float*>(smem_raw), tg.Wmax_p, RP);
+  const KTableHdr* hdr = reinterpret_cast<const KTableHdr*>(tg.table);
+  const int n_tasks = hdr->n_tasks, n_tiles = hdr->n_tiles;
+  float* ck = tg.ckpt ? tg.ckpt + (int64_t)blockIdx.x * kWaves * tg.ckpt_per_wave : nullptr;
+  for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    if constexpr (SC == SC_ACC) {
+      if (tg.flags[tile] == 0) continue;  // only tiles flagged by the fast pass
+    }
+    const TileRef r = decode_tile(tg, n_tasks, tile);
+    const KTask* T = r.task;
+    if constexpr (reverse_mode(MODE))
+      if (task_finished(T)) continue;
+    KTile kt;
+    kt.rec = tg.partials ? tg.partials + T->rec0 + (int64_t)r.local * T->P : nullptr;
+    kt.ck = ck;
+    kt.flag = tg.flags ? tg.flags + tile : nullptr;
+    run_kind<RP, MODE, SC>(T->net, T->inst, tg.ckpt_per_wave, tg.Wmax_p, kt, r.kind, r.wg,
+                           T->inst.s, T->inst.mu, sm);
+    __syncthreads();
+  }
+}
+
+template <typename K>
+static hipError_t set_lds(K kernel, size_t lds) {
+  if (lds <= 65536) return hipSuccess;
+  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds);
+}
+
+template <typename K>
+static int resident_grid(K kernel, int threads, size_t lds) {
+  if (set_lds(kernel, lds) != hipSuccess) return -1;
+  int per_cu = 0, dev = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kernel, threads, lds) !=
+      hipSuccess)
+    return -1;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return -1;
+  return std::max(1, per_cu) * prop.multiProcessorCount;
+}
+
+// Resident workgroups of the kernel that does most of a mode's work.
+template <int RP>
+int table_grid_rp(int mode, int Wmax_p) {
+  if (reverse_mode(mode)) {
+    const size_t lds = ws_lds_floats(RP, Wmax_p) * sizeof(float);
+    return mode == MODE_VJP ? resident_grid(lrnr_grad_ws_table_kernel<RP, true>, kWsThreads, lds)
+                            : resident_grid(lrnr_grad_ws_table_kernel<RP, false>, kWsThreads, lds);
+  }
+  const size_t lds = fused_lds_bytes(RP, Wmax_p);
+  switch (mode) {
+    case MODE_JETS: return resident_grid(lrnr_table_kernel<RP, MODE_JETS, SC_REDO>, kThreads, lds);
+    case MODE_VALUE:
+      return resident_grid(lrnr_table_kernel<RP, MODE_VALUE, SC_REDO>, kThreads, lds);
+    default: return resident_grid(lrnr_table_kernel<RP, MODE_LOSS, SC_REDO>, kThreads, lds);
+  }
+}
+
+template <int RP, int MODE, int SC>
+static hipError_t launch_table_one(const KTableGrid& tg, int grid, hipStream_t stream) {
+  const size_t lds = fused_lds_bytes(RP, tg.Wmax_p);
+  hipError_t e = set_lds(lrnr_table_kernel<RP, MODE, SC>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((lrnr_table_kernel<RP, MODE, SC>), dim3(grid), dim3(kThreads), lds, stream,
+                     tg);
+  return hipGetLastError();
+}
+
+template <int RP, bool VJP>
+static hipError_t launch_table_rev(const KTableGrid& tg, int grid, hipStream_t stream) {
+  const size_t lds = ws_lds_floats(RP, tg.Wmax_p) * sizeof(float);
+  hipError_t e = set_lds(lrnr_grad_ws_table_kernel<RP, VJP>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((lrnr_grad_ws_table_kernel<RP, VJP>), dim3(grid), dim3(kWsThreads), lds,
+                     stream, tg);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // tiles that met |a| > kFastRange are recomputed with ocml's sin/cos
+  return launch_table_one<RP, VJP ? MODE_VJP : MODE_GRAD, SC_ACC>(tg, grid, stream);
+}
+
+// grid: persistent workgroups; the checkpoint slab holds grid * kWaves slabs.
+template <int RP>
+hipError_t launch_table_rp(int mode, const KTableGrid& tg, int grid, hipStream_t stream) {
+  switch (mode) {
+    case MODE_JETS: return launch_table_one<RP, MODE_JETS, SC_REDO>(tg, grid, stream);
+    case MODE_VALUE: return launch_table_one<RP, MODE_VALUE, SC_REDO>(tg, grid, stream);
+    case MODE_LOSS: return launch_table_one<RP, MODE_LOSS, SC_REDO>(tg, grid, stream);
+    case MODE_VJP: return launch_table_rev<RP, true>(tg, grid, stream);
+    default: return launch_table_rev<RP, false>(tg, grid, stream);
+  }
 }
 
 template <int RP>

@@ -3,6 +3,8 @@
 //
 // Both reduction stages add in a fixed order (FP64), so results are bitwise
 // reproducible and do not depend on how many other instances share a launch.
+#include <algorithm>
+
 #include "lrnr_internal.h"
 
 namespace lrnr {
@@ -74,6 +76,106 @@ hipError_t launch_reduce(const KReduce& kr, hipStream_t stream) {
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(reduce_stage2, dim3(gx, kr.B), dim3(bx), 0, stream, kr);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Task tables: one workgroup per task (grid-stride).  Each record element is
+// summed by one thread in the order of the two-stage reduction above (chunks
+// of kRedChunk records, then the chunk sums in order), so a task's results
+// depend only on its own records and match the single-instance path.
+// ---------------------------------------------------------------------------
+constexpr int kTableReduceThreads = 256;
+
+__global__ __launch_bounds__(kTableReduceThreads) void table_reduce_kernel(KTableGrid tg,
+                                                                           int reduce_b,
+                                                                           KAdam adam) {
+  __shared__ double sums[4];
+  __shared__ float gsh[LRNR_MAX_LAYERS * LRNR_MAX_RANK];
+  const KTableHdr* hdr = reinterpret_cast<const KTableHdr*>(tg.table);
+  const int* start = reinterpret_cast<const int*>(tg.table + sizeof(KTableHdr));
+  const KTask* tasks = reinterpret_cast<const KTask*>(tg.table + tg.off_tasks);
+  const int n_tasks = hdr->n_tasks;
+  const int tid = threadIdx.x;
+  for (int t = blockIdx.x; t < n_tasks; t += gridDim.x) {
+    const KTask& T = tasks[t];
+    const bool adam_on = T.m != nullptr;
+    int step = 0;
+    if (adam_on) {
+      step = *T.step;
+      if (T.steps_max > 0 && step >= T.steps_max) continue;  // finished: nothing ran
+    }
+    const int G = start[t + 1] - start[t];
+    const int r_total = T.net.r_total, b_total = T.net.b_total;
+    // loss-only records carry their first four elements only
+    const bool want_b = reduce_b && T.grad_b != nullptr;
+    const bool want_s = T.grad_s != nullptr || adam_on || want_b;
+    const int E = 4 + (want_s ? r_total : 0) + (want_b ? b_total : 0);
+    const int P = T.P;
+    const float* rec = tg.partials + T.rec0;
+    const float* s = T.inst.s;
+    const float* sref = T.s_ref;
+    const bool loc = T.lambda_loc != 0.f && sref != nullptr;
+    const int nchunk = (G + kRedChunk - 1) / kRedChunk;
+    for (int e = tid; e < E; e += kTableReduceThreads) {
+      double acc = 0.0;
+      for (int c = 0; c < nchunk; ++c) {
+        const int r0 = c * kRedChunk, r1 = min(G, r0 + kRedChunk);
+        double cs = 0.0;
+        for (int r = r0; r < r1; ++r) cs += (double)rec[(int64_t)r * P + e];
+        acc += cs;
+      }
+      if (e < 4) {
+        sums[e] = acc;
+      } else if (e < 4 + r_total) {
+        const int k = e - 4;
+        if (loc) acc += (double)T.lambda_loc * sgn(s[k] - sref[k]);
+        const float g = (float)acc;
+        gsh[k] = g;
+        if (T.grad_s) T.grad_s[k] = g;
+      } else {
+        T.grad_b[e - 4 - r_total] = (float)acc;
+      }
+    }
+    __syncthreads();
+    if (tid == 0 && T.loss) {
+      const int64_t n_r = T.inst.n_r, n_0 = T.inst.n_0, n_b = T.inst.n_b;
+      const double ti = n_r ? (double)T.w_r / n_r * sums[0] : 0.0;
+      const double t0 = n_0 ? (double)T.w_0 / n_0 * sums[1] : 0.0;
+      const double tb = n_b ? (double)T.w_b / n_b * sums[2] : 0.0;
+      double tl = 0.0;
+      if (loc)
+        for (int k = 0; k < r_total; ++k) tl += fabs((double)s[k] - (double)sref[k]);
+      T.loss[0] = (float)(ti + t0 + tb + (double)T.lambda_loc * tl);
+      T.loss[1] = (float)ti;
+      T.loss[2] = (float)t0;
+      T.loss[3] = (float)tb;
+    }
+    if (adam_on) {
+      // Adam (Kingma & Ba), bias-corrected, step counted from 1
+      const int stp = step + 1;
+      const float bc1 = (float)(1.0 - pow((double)adam.beta1, (double)stp));
+      const float bc2 = (float)(1.0 - pow((double)adam.beta2, (double)stp));
+      for (int k = tid; k < r_total; k += kTableReduceThreads) {
+        const float gi = gsh[k];
+        const float mi = adam.beta1 * T.m[k] + (1.f - adam.beta1) * gi;
+        const float vi = adam.beta2 * T.v[k] + (1.f - adam.beta2) * gi * gi;
+        T.m[k] = mi;
+        T.v[k] = vi;
+        T.s_upd[k] -= adam.lr * (mi / bc1) / (sqrtf(vi / bc2) + adam.eps);
+      }
+      __syncthreads();  // every thread has read *T.step
+      if (tid == 0) *T.step = stp;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_table_reduce(const KTableGrid& tg, int cap, int reduce_b, KAdam adam,
+                               hipStream_t stream) {
+  const int grid = std::max(1, std::min(cap, 1024));
+  hipLaunchKernelGGL(table_reduce_kernel, dim3(grid), dim3(kTableReduceThreads), 0, stream, tg,
+                     reduce_b, adam);
   return hipGetLastError();
 }
 

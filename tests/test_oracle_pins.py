@@ -212,6 +212,34 @@ def test_grad_s_b_complex_step():
     np.testing.assert_allclose(gb, cb, rtol=1e-11, atol=1e-14)
 
 
+def test_jets_vjp_complex_step():
+    """The oracle's vector-Jacobian product of the jets (used by the
+    differentiation form) against complex-step derivatives of the contracted
+    jets, in s and in b."""
+    net, pts, _ = tiny_case(n=30)
+    xt = pts.xt_r.astype(np.float64)
+    rng = np.random.Generator(np.random.PCG64(5))
+    cot = rng.standard_normal((4, len(xt)))
+    gs, gb = orc.lrnr_jets_vjp(net, net.s, xt, cot)
+    s0 = net.s_flat().astype(np.float64)
+    cs = _complex_step_grad(
+        lambda z: np.sum(cot * orc.lrnr_forward_jets(net, net.split_s(z), xt)), s0)
+    np.testing.assert_allclose(gs, cs, rtol=1e-11, atol=1e-13)
+    b0 = np.concatenate(net.b).astype(np.float64)
+
+    def lb(z):
+        import copy
+        n2 = copy.copy(net)
+        out, o = [], 0
+        for x in net.b:
+            out.append(z[o:o + len(x)])
+            o += len(x)
+        n2.b = out
+        return np.sum(cot * orc.lrnr_forward_jets(n2, net.s, xt))
+
+    np.testing.assert_allclose(gb, _complex_step_grad(lb, b0), rtol=1e-11, atol=1e-13)
+
+
 def test_grad_l1_form_and_locality_fd():
     net, pts, mu = tiny_case(n=25)
     s0 = net.s_flat().astype(np.float64)

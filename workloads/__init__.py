@@ -197,6 +197,18 @@ def batched_case(seed: int = 3, n_inst: int = 64, n: int = 16384) -> Workload:
     return Workload(net, pts, mu, extra={"xt_snap": xt_snap, "r_hat": 32})
 
 
+def instances_case(seed: int = 3, n_inst: int = 64, n: int = 16384) -> Workload:
+    """Differentiation form: the small net, n_inst parameter draws, each
+    instance with its own n interior points and n/8 initial / boundary points.
+    extra['pts'] holds the per-instance Points; ``pts`` is instance 0's."""
+    net = small_lrnr(0, 16).net
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xt_snap = uniform_points(rng, 2048)
+    mu = make_mu(rng, n_inst)
+    per = [make_points(rng, n, n // 8, n // 8) for _ in range(n_inst)]
+    return Workload(net, per[0], mu, extra={"xt_snap": xt_snap, "r_hat": 32, "pts": per})
+
+
 def serving_stream(seed: int = 4, n_req: int = 2000, rate: float = 500.0):
     """Poisson stream of new-mu requests: arrival times (s), mu, point counts
     log-uniform in [1024, 65536], reduced widths drawn from {16, 32, 48}, and a
