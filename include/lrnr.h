@@ -222,6 +222,108 @@ int32_t lrnr_tasks_run(int32_t mode, const lrnr_net* nets, int32_t n_nets,
                        void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Serving engine: continuous batching of new-parameter requests, each solved
+ * by K steps of physics-informed fine-tuning of the coefficients s (Adam on
+ * eq. 3.5-3.7 with the residual of eq. 4.1, through a FastLRNR of Section 2.2
+ * for the sparse back-propagation) followed by the evaluation of the tuned
+ * network on an nx x nt grid (the fast-phase solution of Section 3.2).
+ *
+ * Every request keeps its points, s, Adam moments, step counter, partial
+ * records and grid output in one block of a device arena; a waiting request
+ * is admitted (first come, first served) when a slot, an arena block of its
+ * footprint and tile capacity are free.  Each engine step runs all admitted
+ * requests in one task-table launch (gradient, per-task reduction and Adam),
+ * captured once as a hipGraph of steps_per_launch steps and replayed; the
+ * table in device memory changes only when requests join or leave.  A
+ * request's results are bitwise identical whatever else is in flight.
+ */
+typedef struct lrnr_srv lrnr_srv;
+
+typedef struct lrnr_srv_model {
+  lrnr_net net;          /* device arrays must outlive the engine              */
+  const float* s_init;   /* [dev] [r_total] starting coefficients (and the
+                            locality reference of eq. 3.7)                     */
+} lrnr_srv_model;
+
+typedef struct lrnr_srv_cfg {
+  int32_t n_models;
+  const lrnr_srv_model* models;   /* [host] [n_models]; all ranks <= 32        */
+  int32_t K;                      /* tuning steps per request (>= 1)            */
+  int32_t steps_per_launch;       /* steps per graph launch (>= 1)              */
+  int32_t max_slots;              /* requests admitted at once (<= 4096)        */
+  int32_t max_inflight;           /* step launches queued ahead of the GPU      */
+  int64_t arena_bytes;            /* device memory for request state            */
+  int32_t max_tiles;              /* 256-point tiles in flight (admission cap)  */
+  int32_t use_graph;              /* 1: replay a captured graph; 0: launch      */
+  lrnr_loss_cfg loss;             /* s_ref is ignored (each model's s_init)     */
+  float lr, beta1, beta2, eps;    /* Adam                                       */
+  int32_t grid_nx, grid_nt;       /* evaluation grid x_i = 2 pi i / nx,
+                                     t_j = j / (nt - 1), output [nt][nx]       */
+} lrnr_srv_cfg;
+
+typedef struct lrnr_srv_request {
+  int64_t id;
+  int32_t model;
+  int32_t reserved;
+  float mu[3];                    /* (beta, nu, rho)                            */
+  double arrival;                 /* lrnr_srv_clock() time the request arrived  */
+  /* [host] points; pinned memory (hipHostMalloc) keeps the copies
+     asynchronous.  They must stay valid until the request completes. */
+  const float* xt_r;
+  int64_t n_r;
+  const float* x_0;
+  int64_t n_0;
+  const float* t_b;
+  int64_t n_b;
+  float* u_out;                   /* [host] [nt * nx] grid values, written at completion */
+  float* s_out;                   /* [host] [r_total] tuned s, or NULL           */
+  float* loss_out;                /* [host] [4] loss at the last step, or NULL   */
+} lrnr_srv_request;
+
+typedef struct lrnr_srv_done {
+  int64_t id;
+  double arrival, admitted, done;  /* lrnr_srv_clock() times                    */
+  int32_t model, tiles;
+} lrnr_srv_done;
+
+typedef struct lrnr_srv_stats {
+  int64_t submitted, admitted, completed;
+  int64_t launches, steps, evals, table_uploads;
+  int32_t waiting, active, finishing, peak_active;
+  int64_t arena_used, arena_peak;
+} lrnr_srv_stats;
+
+/* Seconds on the engine's monotonic clock. */
+double lrnr_srv_clock(void);
+
+/* Arena bytes one request of this model and these point counts occupies
+ * (0 when the arguments are invalid). */
+int64_t lrnr_srv_footprint(const lrnr_srv_cfg* cfg, int32_t model, int64_t n_r, int64_t n_0,
+                           int64_t n_b);
+
+/* Creates an engine (allocates its arena and buffers, captures its graph)
+ * on the current device with a stream of its own. */
+int32_t lrnr_srv_create(const lrnr_srv_cfg* cfg, lrnr_srv** out);
+
+/* Queues a request (thread-safe; validation only, no device work).
+ * LRNR_ENOMEM when the request can never fit the arena or tile cap. */
+int32_t lrnr_srv_submit(lrnr_srv* srv, const lrnr_srv_request* req);
+
+/* One scheduling pass, never waiting on the device except to bound the
+ * queued launches: delivers finished requests, admits waiting ones and
+ * queues the next step.  Counts of waiting and admitted requests are
+ * returned through the (nullable) pointers. */
+int32_t lrnr_srv_poll(lrnr_srv* srv, int32_t* n_waiting, int32_t* n_active);
+
+/* Moves up to cap completion records into out[]; *n receives the count. */
+int32_t lrnr_srv_take_done(lrnr_srv* srv, lrnr_srv_done* out, int32_t cap, int32_t* n);
+
+int32_t lrnr_srv_get_stats(const lrnr_srv* srv, lrnr_srv_stats* out);
+
+/* Waits for the device and frees everything the engine owns. */
+int32_t lrnr_srv_destroy(lrnr_srv* srv);
+
+/*
  * FastLRNR construction (Section 2.2, eq. 2.7; construction of Section 4):
  * snapshots of the hidden states z^l at n_snap points for each of the n_s
  * coefficient vectors, POD basis Xi^l (leading r_hat[l] left singular vectors,

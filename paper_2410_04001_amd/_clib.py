@@ -59,6 +59,51 @@ class LrnrTask(C.Structure):
     ]
 
 
+class LrnrSrvModel(C.Structure):
+    _fields_ = [("net", LrnrNet), ("s_init", C.c_void_p)]
+
+
+class LrnrSrvCfg(C.Structure):
+    _fields_ = [
+        ("n_models", C.c_int32), ("models", C.POINTER(LrnrSrvModel)),
+        ("K", C.c_int32), ("steps_per_launch", C.c_int32),
+        ("max_slots", C.c_int32), ("max_inflight", C.c_int32),
+        ("arena_bytes", C.c_int64), ("max_tiles", C.c_int32), ("use_graph", C.c_int32),
+        ("loss", LrnrLossCfg),
+        ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+        ("grid_nx", C.c_int32), ("grid_nt", C.c_int32),
+    ]
+
+
+class LrnrSrvRequest(C.Structure):
+    _fields_ = [
+        ("id", C.c_int64), ("model", C.c_int32), ("reserved", C.c_int32),
+        ("mu", C.c_float * 3), ("arrival", C.c_double),
+        ("xt_r", C.c_void_p), ("n_r", C.c_int64),
+        ("x_0", C.c_void_p), ("n_0", C.c_int64),
+        ("t_b", C.c_void_p), ("n_b", C.c_int64),
+        ("u_out", C.c_void_p), ("s_out", C.c_void_p), ("loss_out", C.c_void_p),
+    ]
+
+
+class LrnrSrvDone(C.Structure):
+    _fields_ = [
+        ("id", C.c_int64), ("arrival", C.c_double), ("admitted", C.c_double),
+        ("done", C.c_double), ("model", C.c_int32), ("tiles", C.c_int32),
+    ]
+
+
+class LrnrSrvStats(C.Structure):
+    _fields_ = [
+        ("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+        ("launches", C.c_int64), ("steps", C.c_int64), ("evals", C.c_int64),
+        ("table_uploads", C.c_int64),
+        ("waiting", C.c_int32), ("active", C.c_int32), ("finishing", C.c_int32),
+        ("peak_active", C.c_int32),
+        ("arena_used", C.c_int64), ("arena_peak", C.c_int64),
+    ]
+
+
 P = C.c_void_p
 I32, I64, F32, SZ = C.c_int32, C.c_int64, C.c_float, C.c_size_t
 NETP, PTSP, CFGP = C.POINTER(LrnrNet), C.POINTER(LrnrPoints), C.POINTER(LrnrLossCfg)
@@ -74,6 +119,14 @@ SIGNATURES = {
     "lrnr_grad_s_batched": (I32, [NETP, I32, P, P, PTSP, CFGP, P, P, P, SZ, P]),
     "lrnr_tasks_workspace_size": (SZ, [I32, NETP, I32, TASKP, I32]),
     "lrnr_tasks_run": (I32, [I32, NETP, I32, TASKP, I32, CFGP, P, SZ, P]),
+    "lrnr_srv_clock": (C.c_double, []),
+    "lrnr_srv_footprint": (I64, [C.POINTER(LrnrSrvCfg), I32, I64, I64, I64]),
+    "lrnr_srv_create": (I32, [C.POINTER(LrnrSrvCfg), C.POINTER(P)]),
+    "lrnr_srv_submit": (I32, [P, C.POINTER(LrnrSrvRequest)]),
+    "lrnr_srv_poll": (I32, [P, C.POINTER(I32), C.POINTER(I32)]),
+    "lrnr_srv_take_done": (I32, [P, C.POINTER(LrnrSrvDone), I32, C.POINTER(I32)]),
+    "lrnr_srv_get_stats": (I32, [P, C.POINTER(LrnrSrvStats)]),
+    "lrnr_srv_destroy": (I32, [P]),
     "fastlrnr_build": (I32, [NETP, P, I32, P, I64, C.POINTER(I32), C.POINTER(P), P]),
     "fastlrnr_get_net": (I32, [P, NETP]),
     "fastlrnr_get_indices": (I32, [P, C.POINTER(I32)]),

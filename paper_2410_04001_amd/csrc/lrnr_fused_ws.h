@@ -27,6 +27,8 @@
 #pragma once
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "lrnr_fused_impl.h"
 
@@ -564,11 +566,20 @@ __global__ __launch_bounds__(kThreads) void lrnr_table_kernel(KTableGrid tg) {
   }
 }
 
+// Raises a kernel's dynamic-LDS limit once per kernel and size (so that
+// launches recorded into a graph make no attribute calls after the first).
 template <typename K>
 static hipError_t set_lds(K kernel, size_t lds) {
   if (lds <= 65536) return hipSuccess;
-  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds);
+  static std::mutex mu;
+  static std::map<const void*, size_t> done;
+  std::lock_guard<std::mutex> lock(mu);
+  const void* key = (const void*)kernel;
+  auto it = done.find(key);
+  if (it != done.end() && it->second >= lds) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) done[key] = lds;
+  return e;
 }
 
 template <typename K>

@@ -121,3 +121,107 @@ def test_status_strings(lib):
     lib.lrnr_forward_jets(C.byref(net), C.c_void_p(16), C.c_void_p(16), 10, C.c_void_p(16), None)
     s = lib.lrnr_status_string(cl.EUNSUPPORTED).decode()
     assert "unsupported" in s and "M[1]=300" in s
+
+
+# ---------------------------------------------------------------- layouts ---
+
+STRUCTS = {
+    "lrnr_net": cl.LrnrNet, "lrnr_points": cl.LrnrPoints, "lrnr_loss_cfg": cl.LrnrLossCfg,
+    "lrnr_task": cl.LrnrTask, "lrnr_srv_model": cl.LrnrSrvModel, "lrnr_srv_cfg": cl.LrnrSrvCfg,
+    "lrnr_srv_request": cl.LrnrSrvRequest, "lrnr_srv_done": cl.LrnrSrvDone,
+    "lrnr_srv_stats": cl.LrnrSrvStats,
+}
+
+
+def test_ctypes_struct_layouts_match_the_header(tmp_path):
+    """sizeof and every field offset of the public structs, as the C compiler
+    lays them out, equal the ctypes views the binding uses."""
+    import shutil
+    import subprocess
+    from _util import ROOT
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "lrnr.h"', "int main(void) {"]
+    for cname, cls in STRUCTS.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", f"{ROOT}/include", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        name, field, val = line.split()
+        got[(name, field)] = int(val)
+    for cname, cls in STRUCTS.items():
+        assert got[(cname, "size")] == C.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
+# ---------------------------------------------------------- task tables ---
+
+def test_tasks_workspace_and_validation(lib):
+    nets = (cl.LrnrNet * 2)(_net(), _net(L=3, M=(2, 48, 40, 1), r=(0, 2, 8, 1)))
+    t = (cl.LrnrTask * 2)()
+    for i in range(2):
+        t[i].net = i
+        t[i].s = t[i].mu = t[i].grad_s = t[i].loss = 16
+        t[i].pts = _pts(1000 * (i + 1), 100, 100)
+    n1 = lib.lrnr_tasks_workspace_size(cl.MODE_GRAD, nets, 2, t, 1)
+    n2 = lib.lrnr_tasks_workspace_size(cl.MODE_GRAD, nets, 2, t, 2)
+    assert 0 < n1 < n2
+    assert lib.lrnr_tasks_workspace_size(cl.MODE_LOSS, nets, 2, t, 2) < n2
+    assert lib.lrnr_tasks_workspace_size(7, nets, 2, t, 2) == 0          # bad mode
+    t[1].net = 2
+    assert lib.lrnr_tasks_workspace_size(cl.MODE_GRAD, nets, 2, t, 2) == 0  # bad net index
+    t[1].net = 1
+    t[1].s = None
+    assert lib.lrnr_tasks_workspace_size(cl.MODE_GRAD, nets, 2, t, 2) == 0  # NULL s
+    t[1].s = 16
+    ws = C.c_void_p(256)
+    st = lib.lrnr_tasks_run(cl.MODE_GRAD, nets, 2, t, 2, C.byref(cl.LrnrLossCfg(0, 1, 1, 1, 0, None)),
+                            ws, n2 - 1, None)
+    assert st == cl.ENOMEM
+
+
+# -------------------------------------------------------------- serving ---
+
+def _srv_cfg(models, **kw):
+    c = cl.LrnrSrvCfg()
+    c.n_models = len(models)
+    c.models = C.cast(models, C.POINTER(cl.LrnrSrvModel))
+    c.K, c.steps_per_launch, c.max_slots, c.max_inflight = 100, 1, 64, 2
+    c.arena_bytes, c.max_tiles, c.use_graph = 1 << 30, 1 << 16, 1
+    c.loss = cl.LrnrLossCfg(0, 1.0, 1.0, 1.0, 0.0, None)
+    c.lr, c.beta1, c.beta2, c.eps = 1e-3, 0.9, 0.999, 1e-8
+    c.grid_nx, c.grid_nt = 256, 100
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def test_serving_footprint_and_config_validation(lib):
+    models = (cl.LrnrSrvModel * 2)()
+    models[0].net = _net(M=(2, 32, 32, 32, 32, 1))
+    models[1].net = _net(M=(2, 48, 48, 48, 48, 1))
+    models[0].s_init = models[1].s_init = 16
+    cfg = _srv_cfg(models)
+    fp = lambda m, n: lib.lrnr_srv_footprint(C.byref(cfg), m, n, n // 8, n // 8)
+    a, b = fp(0, 1024), fp(0, 65536)
+    assert 0 < a < b
+    # points, state, records and the grid output all count
+    assert b - a >= (65536 - 1024) * 8
+    assert fp(0, 1024) >= 256 * 100 * 4
+    assert fp(1, 4096) > fp(0, 4096)            # wider net: longer records
+    assert fp(2, 1024) == 0                     # no such model
+    for bad in ({"K": 0}, {"steps_per_launch": 0}, {"max_slots": 0}, {"max_slots": 5000},
+                {"grid_nt": 1}, {"arena_bytes": 16}, {"lr": 0.0}, {"beta2": 1.0}):
+        c = _srv_cfg(models, **bad)
+        assert lib.lrnr_srv_footprint(C.byref(c), 0, 1024, 128, 128) == 0, bad
+    models[1].s_init = None
+    assert lib.lrnr_srv_footprint(C.byref(cfg), 0, 1024, 128, 128) == 0
