@@ -10,6 +10,7 @@ Prints one JSON line.  Side measurements (FastLRNR vs LRNR on the small net,
 FastLRNR speed-up) are attached under "fastlrnr".
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fast]
+                  [--no-equal-acc] [--no-diff] [--no-serve] [--serve-rates 50,100,...]
 """
 from __future__ import annotations
 
@@ -134,6 +135,223 @@ def run_fast(args, torch, api, wl):
     }
 
 
+def run_equal_accuracy(args, torch, api, wl, big):
+    """FastLRNR against LRNR at equal residual accuracy.  From s_init, Adam
+    (lr 1e-3) with the LRNR gradient and, separately, with the FastLRNR
+    gradient on the same training points; after every step the true (full
+    LRNR) loss on a held-out point set is evaluated outside the timed region.
+    The target is L* = L_0 - (L_0 - L_LRNR@100) / 2; reported: the summed
+    step times each method needs to reach it."""
+    w = wl.equal_accuracy_case(big=big)
+    net = api.DeviceNet.from_net(w.net)
+    s_init = torch.tensor(w.net.s_flat(), device="cuda")
+    pts = api.DevicePoints.from_points(w.pts)
+    held = api.DevicePoints.from_points(w.extra["heldout"])
+    mu = torch.tensor(w.mu[0], device="cuda")
+    cfg = api.LossCfg()
+    fast = api.FastLRNR(net, s_init.reshape(1, -1),
+                        torch.tensor(w.extra["xt_snap"], device="cuda"), w.extra["r_hat"])
+    ws_t, ws_e = api.Workspace(), api.Workspace()
+
+    def held_loss(s):
+        return float(api.residual_loss(net, s, mu, held, cfg, ws=ws_e)[0])
+
+    def train(grad_fn, n_steps):
+        # steps run back to back; the trajectory of s is kept and the held-out
+        # loss is evaluated afterwards
+        s = s_init.clone()
+        m, v = torch.zeros_like(s), torch.zeros_like(s)
+        traj = torch.empty((n_steps + 1, s.numel()), device="cuda")
+        traj[0].copy_(s)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(n_steps)]
+        for k in range(1, n_steps + 1):
+            evs[k - 1][0].record()
+            g = grad_fn(s)
+            api.adam_step(s, m, v, g, k)
+            evs[k - 1][1].record()
+            traj[k].copy_(s)
+        torch.cuda.synchronize()
+        times = np.array([a.elapsed_time(b) for a, b in evs])
+        hist = np.array([held_loss(traj[k].contiguous()) for k in range(n_steps + 1)])
+        return hist, times
+
+    lrnr_grad = lambda s: api.grad_s(net, s, mu, pts, cfg, with_b=False, ws=ws_t)[0]
+    fast_grad = lambda s: fast.grad_s(s, mu, pts, cfg, ws=ws_t)[0]
+    train(lrnr_grad, 3)  # warm-up
+    train(fast_grad, 3)
+    hl, tl = train(lrnr_grad, 100)
+    hf, tf = train(fast_grad, 300)
+    L0, L100 = hl[0], hl[100]
+    target = L0 - 0.5 * (L0 - L100)
+
+    def reach(h, t):
+        idx = np.nonzero(h[1:] <= target)[0]
+        if len(idx) == 0:
+            return None, None
+        k = int(idx[0]) + 1
+        return k, float(np.sum(t[:k]))
+
+    kl, ms_l = reach(hl, tl)
+    kf, ms_f = reach(hf, tf)
+    n_r = pts.counts[0]
+    fast.close()
+    M = w.net.M
+    return {
+        "net": f"{len(M) - 2} hidden x {M[1]} wide, rank {max(w.net.r)}",
+        "r_hat": w.extra["r_hat"], "n_train": n_r, "n_heldout": held.counts[0],
+        "L0": L0, "L_lrnr_100": L100, "L_target": target,
+        "L_fast_100": float(hf[100]), "L_fast_300": float(hf[300]),
+        "lrnr_steps_to_target": kl, "lrnr_ms_to_target": ms_l,
+        "fastlrnr_steps_to_target": kf, "fastlrnr_ms_to_target": ms_f,
+        "time_ratio_lrnr_over_fast": (ms_l / ms_f) if (ms_l and ms_f) else None,
+        "lrnr_step_ms_median": float(np.median(tl)),
+        "fastlrnr_step_ms_median": float(np.median(tf)),
+        "lrnr_pts_per_s": n_r / (float(np.median(tl)) * 1e-3),
+        "fastlrnr_pts_per_s": n_r / (float(np.median(tf)) * 1e-3),
+    }
+
+
+def run_differentiation(args, torch, api, wl):
+    """Differentiation form: 64 instances x 16384 points (own mu and points),
+    FastLRNR r_hat = 32 on the small net, CDRLoss (loss kernel forward,
+    recompute + reverse sweep backward) and torch.optim.Adam, 200 steps."""
+    from paper_2410_04001_amd import autograd as ag
+    B, n = 64, 16384
+    w = wl.instances_case(3, B, n)
+    net = api.DeviceNet.from_net(w.net)
+    s_init = torch.tensor(w.net.s_flat(), device="cuda")
+    fast = api.FastLRNR(net, s_init.reshape(1, -1),
+                        torch.tensor(w.extra["xt_snap"], device="cuda"), 32)
+    dev = lambda a: torch.tensor(np.asarray(a, np.float32), device="cuda").contiguous()
+    P = w.extra["pts"]
+    batch = ag.CDRBatch(fast.net, dev(w.mu), dev(np.stack([p.xt_r for p in P])),
+                        dev(np.stack([p.x_0 for p in P])), dev(np.stack([p.t_b for p in P])),
+                        api.LossCfg())
+    s = torch.nn.Parameter(s_init.repeat(B, 1).contiguous())
+    opt = torch.optim.Adam([s], lr=1e-3)
+
+    def step():
+        opt.zero_grad(set_to_none=False)
+        loss = ag.cdr_loss(s, batch)
+        loss.sum().backward()
+        opt.step()
+        return loss
+
+    l0 = step().detach().clone()
+    for _ in range(4):
+        step()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(195):
+        loss = step()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / 195
+    ms_grad = time_calls(torch, lambda: batch.loss_and_grad(s.detach()), 20, 3)
+    fast.close()
+    return {
+        "workload": "64 instances x 16384 interior (+2048 IC, +2048 BC) points each, own mu and "
+                    "points; FastLRNR r_hat=32 on the 64-wide rank-8 net; 200 Adam steps lr 1e-3",
+        "ms_per_adam_step": ms,
+        "pts_per_s": B * n / (ms * 1e-3),
+        "fused_loss_grad_ms": ms_grad,
+        "fused_loss_grad_pts_per_s": B * n / (ms_grad * 1e-3),
+        "loss_sum_first": float(l0.sum()), "loss_sum_last": float(loss.detach().sum()),
+    }
+
+
+def run_serving(args, torch, api, wl):
+    """Serving form: Poisson streams of new-mu requests (N log-uniform in
+    [1024, 65536], r_hat drawn from {16, 32, 48}, mu from the CDR law), each
+    tuned by K = 100 Adam steps of FastLRNR sparse backprop and evaluated on
+    a 256 x 100 grid, through the native continuous-batching engine."""
+    from paper_2410_04001_amd import serving
+    base = wl.fast_case(2, n=16)
+    net = api.DeviceNet.from_net(base.net)
+    s0 = torch.tensor(base.net.s_flat(), device="cuda")
+    xs = torch.tensor(base.extra["xt_snap"], device="cuda")
+    widths = [16, 32, 48]
+    fasts = [api.FastLRNR(net, s0.reshape(1, -1), xs, rh) for rh in widths]
+    srv = serving.Server([(f.net, s0) for f in fasts], K=100,
+                         steps_per_launch=args.serve_steps_per_launch, max_slots=256,
+                         max_inflight=2, arena_bytes=2 << 30, max_tiles=1 << 17)
+    n_req = args.serve_requests
+    st = wl.serving_stream(4, n_req, 1.0)
+    reqs = []
+    for i in range(n_req):
+        pts = wl.request_points(st["pt_seed"][i], int(st["n"][i]))
+        reqs.append(srv.request(i, widths.index(int(st["r_hat"][i])), st["mu"][i], pts))
+    # a short unmeasured stream first (code objects, pinned pools)
+    serving.replay(srv, reqs[:32], st["arrival"][:32] / 2000.0)
+    rows = []
+    for rate in args.serve_rates:
+        done, wall = serving.replay(srv, reqs, st["arrival"] / rate)
+        row = serving.latency_summary(done, wall)
+        row["offered_req_per_s"] = rate
+        row["tuning_pt_steps_per_s"] = row.pop("colloc_pts_per_s") * 100
+        rows.append(row)
+        print(f"# serving rate {rate}: p50 {row['p50_ms']:.2f} ms p99 {row['p99_ms']:.2f} ms "
+              f"achieved {row['req_per_s']:.1f} req/s", file=sys.stderr, flush=True)
+    stats = srv.stats()
+    srv.close()
+    for f in fasts:
+        f.close()
+    mean_n = float(np.mean(st["n"]))
+    return {
+        "workload": f"{n_req} requests per rate; N log-uniform [1024, 65536] (mean {mean_n:.0f}), "
+                    "N/8 IC and BC points; r_hat in {16, 32, 48} on the 64-wide rank-8 net; "
+                    "K=100 Adam steps then a 256x100 grid evaluation",
+        "steps_per_launch": args.serve_steps_per_launch,
+        "rates": rows,
+        "engine": {k: stats[k] for k in ("launches", "steps", "evals", "table_uploads",
+                                          "peak_active", "arena_peak")},
+    }
+
+
+KERNEL_SOURCES = ("lrnr_internal.h", "lrnr_fused_impl.h", "lrnr_fused_ws.h", "lrnr_fused_rp20.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lrnr_grad_ws_N262144_w256_r20_traffic.md")
+
+
+def kernel_source_sha():
+    """SHA-256 over the sources of the working-size gradient kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2410_04001_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter summary, or None when
+    the kernel sources changed after the counters were taken."""
+    try:
+        fields = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith(("#", "|", "`")):
+                k, v = line.split(":", 1)
+                if v.split():
+                    fields[k.strip().strip("-* ")] = v.split()[0].strip("`")
+        if fields.get("source_sha256") != kernel_source_sha():
+            return None
+        return float(fields["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_calibration(torch):
+    """A plain device copy of known size (1 GiB read, 1 GiB written) for
+    scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    a = torch.ones(2 ** 28, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 2 ** 30, "copy_bytes_written": 2 ** 30}), flush=True)
+
+
 def cpu_baseline(w, wl):
     """The FP64 oracle on a bounded sample of the same workload."""
     from oracle import lrnr_oracle as orc
@@ -166,6 +384,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fast", action="store_true")
+    ap.add_argument("--no-equal-acc", action="store_true")
+    ap.add_argument("--no-diff", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rates", type=lambda x: [float(v) for v in x.split(",")],
+                    default=[50, 100, 200, 500, 1000, 2000])
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-steps-per-launch", type=int, default=1)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -178,6 +405,9 @@ def main():
     from paper_2410_04001_amd import api
 
     torch.cuda.init()
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     r = run_lrnr(args, torch, api, wl)
     n_r, n_0, n_b = r["counts"]
     fast = None if args.no_fast else run_fast(args, torch, api, wl)
@@ -206,14 +436,21 @@ def main():
             "peak": FP32_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": r["achieved_tflops"] / FP32_MFMA_PEAK_TFLOPS,
-            "traffic": None,
-            "kernel": "lrnr_fused_kernel<20, MODE_GRAD>",
+            "traffic": measured_traffic(),
+            "kernel": "lrnr_grad_ws_kernel<20> (+ relaunch of flagged tiles)",
             "kernel_ms_avg": r["kernel_ms_avg"],
             "flops_per_launch": r["flops_per_launch"],
         },
     }
     if fast is not None:
         out["fastlrnr"] = fast
+    if not args.no_equal_acc:
+        out["equal_accuracy"] = [run_equal_accuracy(args, torch, api, wl, big)
+                                 for big in (False, True)]
+    if not args.no_diff:
+        out["differentiation"] = run_differentiation(args, torch, api, wl)
+    if not args.no_serve:
+        out["serving"] = run_serving(args, torch, api, wl)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(r["w"], wl)
     print(json.dumps(out), flush=True)

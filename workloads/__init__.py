@@ -186,6 +186,21 @@ def fast_case(seed: int = 2, n: int = 65536, n_snap: int = 2048, r_hat: int = 32
     return Workload(net, pts, mu, extra={"xt_snap": xt_snap, "r_hat": r_hat})
 
 
+def equal_accuracy_case(big: bool = False, seed: int = 2, n: int = 65536,
+                        n_snap: int = 2048, r_hat: int = 32) -> Workload:
+    """FastLRNR against LRNR at equal residual accuracy: the small net (or,
+    with ``big``, the 256-wide rank-20 net) with snapshot points, training
+    points, one parameter draw and a held-out point set of the same size,
+    all drawn from ``seed`` in that order."""
+    net = (big_lrnr(1, 16) if big else small_lrnr(0, 16)).net
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xt_snap = uniform_points(rng, n_snap)
+    pts = make_points(rng, n, n // 8, n // 8)
+    mu = make_mu(rng, 1)
+    held = make_points(rng, n, n // 8, n // 8)
+    return Workload(net, pts, mu, extra={"xt_snap": xt_snap, "r_hat": r_hat, "heldout": held})
+
+
 def batched_case(seed: int = 3, n_inst: int = 64, n: int = 16384) -> Workload:
     """Many-instance case: the small net, n_inst parameter draws sharing one
     point set of n interior points."""
