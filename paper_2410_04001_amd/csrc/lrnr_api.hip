@@ -46,7 +46,7 @@ int32_t make_knet(const lrnr_net* net, KNet* k, int* RP, int* Wmax_p) {
   if (!net->U || !net->V || !net->b) return fail(LRNR_EINVAL, "U, V or b is NULL");
   *k = KNet{};
   k->L = L;
-  int oU = 0, oV = 0, oB = 0, oS = 0, rmax = 1, wmax = 4;
+  int oU = 0, oV = 0, oB = 0, oS = 0, rmax = 1, wmax = 16;
   for (int l = 0; l <= L; ++l) k->M[l] = net->M[l];
   for (int l = 1; l <= L; ++l) {
     const int Ml = net->M[l], Mp = net->M[l - 1], rl = net->r[l];
@@ -67,7 +67,7 @@ int32_t make_knet(const lrnr_net* net, KNet* k, int* RP, int* Wmax_p) {
     oB += Ml;
     oS += rl;
     if (l >= 2 && l <= L - 1 && rl > rmax) rmax = rl;
-    if (l <= L - 1) wmax = std::max(wmax, (Ml + 3) & ~3);
+    if (l <= L - 1) wmax = std::max(wmax, (Ml + 15) & ~15);
   }
   k->r_total = oS;
   k->b_total = oB;

@@ -456,7 +456,8 @@ template <int NT>
 __device__ void stage_layer(const KNet& net, const float* __restrict__ s, int l, int KI,
                             int KO, float* __restrict__ Us, float* __restrict__ Vs,
                             float* __restrict__ bs, float* __restrict__ ss) {
-  const int W = net.M[l], Wp = (W + 3) & ~3, rl = net.r[l], ro = net.r[l + 1];
+  // rows padded to a multiple of 16 (value-only tiles step over 16 neurons)
+  const int W = net.M[l], Wp = (W + 15) & ~15, rl = net.r[l], ro = net.r[l + 1];
   const float* __restrict__ U = net.U + net.offU[l];
   const float* __restrict__ V = net.V + net.offV[l + 1];
   const float* __restrict__ b = net.b + net.offB[l];

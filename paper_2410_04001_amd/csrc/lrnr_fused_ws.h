@@ -2,28 +2,31 @@
 // arXiv 2410.04001: eq. 2.1-2.2 / 2.8 chain with jets, eq. 4.1 residual,
 // eq. 3.5-3.7 loss, reverse sweep to s and b).
 //
-// Why: at the register footprint of rank-20 jets (about 500 registers per
-// lane when one wave does everything) only one wave fits on a SIMD, and one
-// wave never overlaps its MFMA and VALU work.  Here every 64-point tile is
-// owned by a pair of waves on the same SIMD (waves w and w + 4 of the
-// 8-wave workgroup):
+// Every 64-point tile is owned by four waves, one per role, on one SIMD
+// (waves w, w + 4, w + 8, w + 12 of the 16-wave workgroup):
 //
-//   forward   M wave: a = U (s y) + b for the next neuron group  (MFMA)
-//             E wave: sin jets of a, then y' += V^T z              (VALU, MFMA)
-//   reverse   M wave: a (recomputed) and zbar = V ybar for the next group
-//             E wave: adjoint of the sin jets, db row, wbar += U^T abar
+//          forward                          reverse
+//   M1     a = U (s y) + b     (MFMA)       a = U (s y) + b        (MFMA)
+//   S0/S1  sin jets of half of the group    S0: adjoint of the sin jets and
+//          each (VALU)                      the db row (VALU); S1: wbar +=
+//                                           U^T abar (MFMA), then ds, ybar
+//   M2     y' += V^T z (MFMA), then the     zbar = V ybar          (MFMA)
+//          output layer and the residual
 //
-// a and zbar cross from M to E through a double-buffered LDS slot per pair;
-// one workgroup barrier per neuron group paces the pipeline, so the M wave's
-// MFMAs for group g+1 run while the E wave works on group g.  Each role holds
-// only its own rank-sized state (at most about 200 registers), so two waves
-// fit per SIMD.  The role loops are separate code paths with the same number
-// of barriers (the hardware barrier counts waves, not program locations), so
-// the register allocator sees the roles' live ranges apart.
+// Both sweeps are three-stage pipelines over 4-neuron groups (producers on
+// group g, the middle stage on g - 1, the consumer on g - 2); values cross
+// between roles through double-buffered LDS slots and one workgroup barrier
+// ends every step.  No role holds more than one rank-sized jet array
+// (4 x RP registers), so four waves fit per SIMD.  On this hardware FP32
+// MFMA and VALU work of one SIMD do not overlap (measured), so the split does
+// not hide the VALU work; it hides latency: while one wave waits on an LDS
+// read, a barrier or a dependent MFMA, another wave of the SIMD issues.
+// The role loops are separate code paths with equal barrier counts (the
+// hardware barrier counts waves, not program locations).
 //
-// Between layers the reduced jets travel through the global checkpoint slab
-// of the pair: E writes y^{l+1} (forward) and ybar^l (reverse), M reads them
-// after the next barrier.
+// Between layers the reduced jets travel through the tile's global
+// checkpoint slab: M2 writes y^{l+1} (forward), S1 writes ybar^l (reverse),
+// and M1 / M2 read them after the next barrier.
 #pragma once
 
 #include <algorithm>
@@ -34,211 +37,423 @@
 
 namespace lrnr {
 
-constexpr int kWsWaves = 8;
+constexpr int kWsWaves = 16;
 constexpr int kWsThreads = 64 * kWsWaves;
-constexpr int kSlotF4 = 8;                      // f4 per lane in one exchange slot
-constexpr int kSlotFloats = kSlotF4 * 64 * 4;   // floats in one exchange slot
+constexpr int kXFloats = 4 * 64 * 4;   // one exchange slot: 4 f4 per lane
+
+typedef float f2 __attribute__((ext_vector_type(2)));
 
 struct SmemWS {
   float* Us;
   float* Vs;
   float* bs;
   float* ss;
-  float* xbuf;  // [4 pairs][2 slots][kSlotFloats]
+  float* xa;    // [4 tiles][2 slots][kXFloats]  a                     (M1 -> S)
+  float* xz;    // [4 tiles][2 slots][kXFloats]  z (S -> M2) / zbar (M2 -> S0)
+  float* xg;    // [4 tiles][2 slots][kXFloats]  abar                  (S0 -> S1)
   float* bbar;  // [4][Wmax_p]
   float* sbar;  // [4][RP]
-  float* lw;    // [4][4]
+  float* lw;    // [16] loss sums, [16] range flags
 };
 
 inline size_t ws_lds_floats(int RP, int Wmax_p) {
-  return (size_t)Wmax_p * RP * 2 + Wmax_p + RP + (size_t)4 * 2 * kSlotFloats +
-         (size_t)4 * Wmax_p + (size_t)4 * RP + 16;
+  return (size_t)Wmax_p * RP * 2 + Wmax_p + RP + (size_t)3 * 4 * 2 * kXFloats +
+         (size_t)4 * Wmax_p + (size_t)4 * RP + 32;
+}
+
+__device__ __forceinline__ SmemWS ws_smem(float* base, int Wm, int RP) {
+  SmemWS sm;
+  sm.Us = base;
+  sm.Vs = sm.Us + Wm * RP;
+  sm.bs = sm.Vs + Wm * RP;
+  sm.ss = sm.bs + Wm;
+  sm.xa = sm.ss + RP;
+  sm.xz = sm.xa + 4 * 2 * kXFloats;
+  sm.xg = sm.xz + 4 * 2 * kXFloats;
+  sm.bbar = sm.xg + 4 * 2 * kXFloats;
+  sm.sbar = sm.bbar + 4 * Wm;
+  sm.lw = sm.sbar + 4 * RP;
+  return sm;
 }
 
 template <int N>
-__device__ __forceinline__ void xput(float* __restrict__ slot, int lane, const f4 (&v)[N],
-                                     int first = 0) {
+__device__ __forceinline__ void xput(float* __restrict__ slot, int lane, const f4 (&v)[N]) {
 #pragma unroll
-  for (int i = 0; i < N; ++i)
-    *reinterpret_cast<f4*>(slot + ((first + i) * 64 + lane) * 4) = v[i];
+  for (int i = 0; i < N; ++i) *reinterpret_cast<f4*>(slot + (i * 64 + lane) * 4) = v[i];
 }
 
 template <int N>
-__device__ __forceinline__ void xget(const float* __restrict__ slot, int lane, f4 (&v)[N],
-                                     int first = 0) {
+__device__ __forceinline__ void xget(const float* __restrict__ slot, int lane, f4 (&v)[N]) {
 #pragma unroll
-  for (int i = 0; i < N; ++i)
-    v[i] = *reinterpret_cast<const f4*>(slot + ((first + i) * 64 + lane) * 4);
+  for (int i = 0; i < N; ++i) v[i] = *reinterpret_cast<const f4*>(slot + (i * 64 + lane) * 4);
 }
 
-// ---------------------------------------------------------------------------
-// Forward, one hidden layer.  M: y holds s*y^l (input); E: y accumulates y^{l+1}.
-// ---------------------------------------------------------------------------
-template <int NJ, int RGM, int RGI>
-__device__ __forceinline__ void ws_fwd_M(const SmemWS& sm, float* xb, int G, int li, int lane,
-                                         f4 (&y)[NJ][RGM]) {
+// Half h (neurons 2h, 2h+1) of each f4 in a slot.
+template <int N>
+__device__ __forceinline__ void xput2(float* __restrict__ slot, int lane, int h,
+                                      const f2 (&v)[N]) {
 #pragma unroll
-  for (int g = 0; g < RGI; ++g) {
-    const f4 s4 = *reinterpret_cast<const f4*>(sm.ss + 4 * g);
+  for (int i = 0; i < N; ++i) *reinterpret_cast<f2*>(slot + (i * 64 + lane) * 4 + 2 * h) = v[i];
+}
+
+template <int N>
+__device__ __forceinline__ void xget2(const float* __restrict__ slot, int lane, int h,
+                                      f2 (&v)[N]) {
 #pragma unroll
-    for (int c = 0; c < NJ; ++c) y[c][g] *= s4;
+  for (int i = 0; i < N; ++i)
+    v[i] = *reinterpret_cast<const f2*>(slot + (i * 64 + lane) * 4 + 2 * h);
+}
+
+// sin jets of two neurons (the policy of sincos4: hardware sin/cos when the
+// whole wave is within kHwRange, else the Cody-Waite polynomial)
+template <int NJ>
+__device__ __forceinline__ void sigma_fwd2(const f2 (&a)[NJ], f2 (&z)[NJ], float& amax) {
+  const float m = fmaxf(fabsf(a[0][0]), fabsf(a[0][1]));
+  amax = fmaxf(amax, m);
+  f2 sn, cs;
+  if (__all(m <= kHwRange)) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      float sj, cj;
+      sincos_hw(a[0][j], sj, cj);
+      sn[j] = sj;
+      cs[j] = cj;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      float sj, cj;
+      sincos_fast(a[0][j], sj, cj);
+      sn[j] = sj;
+      cs[j] = cj;
+    }
   }
-  f4 a[NJ];
-  u_side<NJ, RGM, RGI>(sm.Us, sm.bs, 0, li, y, a);
-  xput<NJ>(xb, lane, a);
-  __syncthreads();
-  for (int g = 0; g < G; ++g) {
-    if (g + 1 < G) {
-      u_side<NJ, RGM, RGI>(sm.Us, sm.bs, 4 * (g + 1), li, y, a);
-      xput<NJ>(xb + ((g + 1) & 1) * kSlotFloats, lane, a);
+  z[0] = sn;
+  if constexpr (NJ == 4) {
+    const f2 ax = a[1];
+    z[1] = cs * ax;
+    z[2] = cs * a[2];
+    z[3] = cs * a[3] - sn * ax * ax;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Contractions of one 4-neuron group with the factor entries read from LDS
+// one rank group (or one neuron) ahead of the MFMAs that use them, which keeps
+// the operand registers of a role small.
+// ---------------------------------------------------------------------------
+
+// out = R[w0..w0+3] y (+ bias): R row-major [W][4 RG], y in rank space
+template <int NJ, int RGM, int RG, bool BIAS>
+__device__ __forceinline__ void rows_times(const float* __restrict__ R,
+                                           const float* __restrict__ bs, int w0, int li,
+                                           const f4 (&y)[NJ][RGM], f4 (&out)[NJ]) {
+  constexpr int K = 4 * RG;
+  const float* row = R + (w0 + li) * K;
+  if constexpr (BIAS)
+    out[0] = *reinterpret_cast<const f4*>(bs + w0);
+  else
+    out[0] = zero4();
+#pragma unroll
+  for (int c = 1; c < NJ; ++c) out[c] = zero4();
+  f4 nxt = *reinterpret_cast<const f4*>(row);
+#pragma unroll
+  for (int g = 0; g < RG; ++g) {
+    const f4 cur = nxt;
+    if (g + 1 < RG) nxt = *reinterpret_cast<const f4*>(row + 4 * (g + 1));
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int c = 0; c < NJ; ++c) out[c] = mfma4(cur[kk], y[c][g][kk], out[c]);
+  }
+}
+
+// acc += R[w0..w0+3]^T v: R row-major [W][4 RG], v per neuron (f4 of 4 neurons)
+template <int NJ, int RGM, int RG>
+__device__ __forceinline__ void rows_t_times(const float* __restrict__ R, int w0, int li,
+                                             const f4 (&v)[NJ], f4 (&acc)[NJ][RGM]) {
+  constexpr int K = 4 * RG;
+  float nxt[RG];
+#pragma unroll
+  for (int g = 0; g < RG; ++g) nxt[g] = R[w0 * K + 4 * g + li];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float cur[RG];
+#pragma unroll
+    for (int g = 0; g < RG; ++g) cur[g] = nxt[g];
+    if (j + 1 < 4) {
+#pragma unroll
+      for (int g = 0; g < RG; ++g) nxt[g] = R[(w0 + j + 1) * K + 4 * g + li];
+    }
+#pragma unroll
+    for (int g = 0; g < RG; ++g)
+#pragma unroll
+      for (int c = 0; c < NJ; ++c) acc[c][g] = mfma4(cur[g], v[c][j], acc[c][g]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Role loops of one hidden layer: `steps` steps, each ending in a workgroup
+// barrier; step k works on neuron block k - (stage of the role) when that
+// exists.  A block is NG 4-neuron groups: NG = 1 for the four-jet interior
+// tiles, NG = 4 for the value-only IC/BC tiles, so every exchange slot holds
+// NJ x NG = 4 f4 per lane and value-only tiles need a quarter of the steps.
+// Slot entry q * NJ + c is jet c of group q.
+// ---------------------------------------------------------------------------
+
+// M1: a = U (s y) + b for block k (both sweeps)
+template <int NJ, int RGM, int RGI, int NG>
+__device__ __forceinline__ void m1_loop(const SmemWS& sm, float* xa, int Gs, int steps, int li,
+                                        int lane, const f4 (&ys)[NJ][RGM]) {
+  for (int k = 0; k < steps; ++k) {
+    if (k < Gs) {
+      f4 a[NJ * NG];
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        f4 aq[NJ];
+        rows_times<NJ, RGM, RGI, true>(sm.Us, sm.bs, 4 * (k * NG + q), li, ys, aq);
+#pragma unroll
+        for (int c = 0; c < NJ; ++c) a[q * NJ + c] = aq[c];
+      }
+      xput<NJ * NG>(xa + (k & 1) * kXFloats, lane, a);
     }
     __syncthreads();
   }
 }
 
-template <int NJ, int RGM, int RGO>
-__device__ __forceinline__ void ws_fwd_E(const SmemWS& sm, const float* xb, int G, int li,
-                                         int lane, f4 (&y)[NJ][RGM], float& amax) {
+// S0 / S1 forward: sin jets of neurons 2h, 2h+1 of every group of block k - 1
+template <int NJ, int NG>
+__device__ __forceinline__ void s_fwd_loop(const float* xa, float* xz, int Gs, int lane, int h,
+                                           float& amax) {
+  for (int k = 0; k < Gs + 2; ++k) {
+    if (k >= 1 && k <= Gs) {
+      f2 a[NJ * NG], z[NJ * NG];
+      xget2<NJ * NG>(xa + ((k - 1) & 1) * kXFloats, lane, h, a);
 #pragma unroll
-  for (int c = 0; c < NJ; ++c)
+      for (int q = 0; q < NG; ++q) {
+        f2 aq[NJ], zq[NJ];
 #pragma unroll
-    for (int g = 0; g < RGO; ++g) y[c][g] = zero4();
-  __syncthreads();
-  for (int g = 0; g < G; ++g) {
-    f4 a[NJ], z[NJ];
-    xget<NJ>(xb + (g & 1) * kSlotFloats, lane, a);
-    sigma_fwd<NJ, false>(a, z, amax);
-    v_side<NJ, RGM, RGO>(sm.Vs, 4 * g, li, z, y);
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Reverse, one hidden layer.  M: ys = s*y^l and yb = ybar^{l+1}; E: wb.
-// ---------------------------------------------------------------------------
-template <int NJ, int RGM, int RGI, int RGO>
-__device__ __forceinline__ void ws_bwd_M(const SmemWS& sm, float* xb, int G, int li, int lane,
-                                         f4 (&ys)[NJ][RGM], const f4 (&yb)[NJ][RGM]) {
+        for (int c = 0; c < NJ; ++c) aq[c] = a[q * NJ + c];
+        sigma_fwd2<NJ>(aq, zq, amax);
 #pragma unroll
-  for (int g = 0; g < RGI; ++g) {
-    const f4 s4 = *reinterpret_cast<const f4*>(sm.ss + 4 * g);
-#pragma unroll
-    for (int c = 0; c < NJ; ++c) ys[c][g] *= s4;
-  }
-  f4 a[NJ], zb[NJ];
-  u_side<NJ, RGM, RGI>(sm.Us, sm.bs, 0, li, ys, a);
-  v_rev<NJ, RGM, RGO>(sm.Vs, 0, li, yb, zb);
-  xput<NJ>(xb, lane, a);
-  xput<NJ>(xb, lane, zb, NJ);
-  __syncthreads();
-  for (int g = 0; g < G; ++g) {
-    if (g + 1 < G) {
-      float* slot = xb + ((g + 1) & 1) * kSlotFloats;
-      u_side<NJ, RGM, RGI>(sm.Us, sm.bs, 4 * (g + 1), li, ys, a);
-      v_rev<NJ, RGM, RGO>(sm.Vs, 4 * (g + 1), li, yb, zb);
-      xput<NJ>(slot, lane, a);
-      xput<NJ>(slot, lane, zb, NJ);
+        for (int c = 0; c < NJ; ++c) z[q * NJ + c] = zq[c];
+      }
+      xput2<NJ * NG>(xz + ((k - 1) & 1) * kXFloats, lane, h, z);
     }
     __syncthreads();
   }
 }
 
-template <int NJ, int RGM, int RGI>
-__device__ __forceinline__ void ws_bwd_E(const SmemWS& sm, const float* xb, int G, int li,
-                                         int lane, f4 (&wb)[NJ][RGM],
-                                         float* __restrict__ bbar_row, float& amax) {
+// M2 forward: y' += V^T z for block k - 2
+template <int NJ, int RGM, int RGO, int NG>
+__device__ __forceinline__ void m2_fwd_loop(const SmemWS& sm, const float* xz, int Gs, int li,
+                                            int lane, f4 (&y)[NJ][RGM]) {
+  for (int k = 0; k < Gs + 2; ++k) {
+    if (k >= 2) {
+      f4 z[NJ * NG];
+      xget<NJ * NG>(xz + (k & 1) * kXFloats, lane, z);
 #pragma unroll
-  for (int c = 0; c < NJ; ++c)
+      for (int q = 0; q < NG; ++q) {
+        f4 zq[NJ];
 #pragma unroll
-    for (int g = 0; g < RGI; ++g) wb[c][g] = zero4();
+        for (int c = 0; c < NJ; ++c) zq[c] = z[q * NJ + c];
+        rows_t_times<NJ, RGM, RGO>(sm.Vs, 4 * ((k - 2) * NG + q), li, zq, y);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// M2 reverse: zbar = V ybar for block k
+template <int NJ, int RGM, int RGO, int NG>
+__device__ __forceinline__ void m2_bwd_loop(const SmemWS& sm, float* xz, int Gs, int li,
+                                            int lane, const f4 (&yb)[NJ][RGM]) {
+  for (int k = 0; k < Gs + 2; ++k) {
+    if (k < Gs) {
+      f4 zb[NJ * NG];
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        f4 zq[NJ];
+        rows_times<NJ, RGM, RGO, false>(sm.Vs, nullptr, 4 * (k * NG + q), li, yb, zq);
+#pragma unroll
+        for (int c = 0; c < NJ; ++c) zb[q * NJ + c] = zq[c];
+      }
+      xput<NJ * NG>(xz + (k & 1) * kXFloats, lane, zb);
+    }
+    __syncthreads();
+  }
+}
+
+// S0 reverse: adjoint of the sin jets and the db row for block k - 1
+template <int NJ, int NG>
+__device__ __forceinline__ void s0_bwd_loop(const float* xa, const float* xz, float* xg, int Gs,
+                                            int lane, float* __restrict__ bbar_row,
+                                            float& amax) {
   const int comp = sum4_component(lane);
-  __syncthreads();
-  for (int g = 0; g < G; ++g) {
-    const float* slot = xb + (g & 1) * kSlotFloats;
-    f4 a[NJ], zb[NJ], ab[NJ];
-    xget<NJ>(slot, lane, a);
-    xget<NJ>(slot, lane, zb, NJ);
-    sigma_bwd<NJ, false>(a, zb, ab, amax);
-    const float bsum = wave_sum4(ab[0], lane);
-    if ((lane & 15) == 0) bbar_row[4 * g + comp] = bsum;
-    ut_side<NJ, RGM, RGI>(sm.Us, 4 * g, li, ab, wb);
+  for (int k = 0; k < Gs + 2; ++k) {
+    if (k >= 1 && k <= Gs) {
+      const int slot = ((k - 1) & 1) * kXFloats;
+      f4 a[NJ * NG], zb[NJ * NG], ab[NJ * NG];
+      xget<NJ * NG>(xa + slot, lane, a);
+      xget<NJ * NG>(xz + slot, lane, zb);
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        f4 aq[NJ], zq[NJ], gq[NJ];
+#pragma unroll
+        for (int c = 0; c < NJ; ++c) {
+          aq[c] = a[q * NJ + c];
+          zq[c] = zb[q * NJ + c];
+        }
+        sigma_bwd<NJ, false>(aq, zq, gq, amax);
+#pragma unroll
+        for (int c = 0; c < NJ; ++c) ab[q * NJ + c] = gq[c];
+      }
+      xput<NJ * NG>(xg + slot, lane, ab);
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        const float bsum = wave_sum4(ab[q * NJ], lane);
+        if ((lane & 15) == 0) bbar_row[4 * ((k - 1) * NG + q) + comp] = bsum;
+      }
+    }
     __syncthreads();
   }
 }
 
+// S1 reverse: wbar += U^T abar for block k - 2
+template <int NJ, int RGM, int RGI, int NG>
+__device__ __forceinline__ void s1_bwd_loop(const SmemWS& sm, const float* xg, int Gs, int li,
+                                            int lane, f4 (&wb)[NJ][RGM]) {
+  for (int k = 0; k < Gs + 2; ++k) {
+    if (k >= 2) {
+      f4 ab[NJ * NG];
+      xget<NJ * NG>(xg + (k & 1) * kXFloats, lane, ab);
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        f4 gq[NJ];
+#pragma unroll
+        for (int c = 0; c < NJ; ++c) gq[c] = ab[q * NJ + c];
+        rows_t_times<NJ, RGM, RGI>(sm.Us, 4 * ((k - 2) * NG + q), li, gq, wb);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// One rank group of a checkpointed jet array.
+template <int NJ, int RGM>
+__device__ __forceinline__ void ckpt_load_g(const float* __restrict__ base, int lane, int g,
+                                            f4 (&y)[NJ]) {
+#pragma unroll
+  for (int c = 0; c < NJ; ++c)
+    y[c] = *reinterpret_cast<const f4*>(base + ((c * RGM + g) * 64 + lane) * 4);
+}
+
+// Rank group 0 of the input layer's jets (V^1T (x, t) and its constant jets).
+template <int NJ>
+__device__ __forceinline__ void input_jets_g0(const KNet& net, float x, float t, f4 (&y)[NJ]) {
+  const int r1 = net.r[1];
+  const float* V1 = net.V + net.offV[1];
+  const float v00 = V1[0], v10 = V1[r1];
+  const float v01 = r1 > 1 ? V1[1] : 0.f, v11 = r1 > 1 ? V1[r1 + 1] : 0.f;
+  y[0] = f4{v00 * x + v10 * t, v01 * x + v11 * t, 0.f, 0.f};
+  if constexpr (NJ == 4) {
+    y[1] = f4{v00, v01, 0.f, 0.f};
+    y[2] = f4{v10, v11, 0.f, 0.f};
+    y[3] = zero4();
+  }
+}
+
 // ---------------------------------------------------------------------------
-// Workgroup driver (MODE_GRAD, fast sin/cos with range tracking)
+// Workgroup driver (MODE_GRAD / MODE_VJP, fast sin/cos with range tracking)
 // ---------------------------------------------------------------------------
 template <int RP, int NJ, bool VJP>
 __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave, int Wmax_p,
                        const KTile& tile, int kind, int wg, const float* __restrict__ s,
                        const float* __restrict__ mu, const SmemWS& sm) {
   constexpr int RGM = RP / 4;
+  constexpr int NG = 4 / NJ;                    // 4-neuron groups per step
   constexpr int64_t kSlot = 4 * RGM * 64 * 4;  // floats per checkpoint slot
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 3;
-  const int pair = wave & 3;
-  const bool isM = wave < 4;
+  const int trip = wave & 3, role = wave >> 2;  // 0: M1, 1: M2, 2: S0, 3: S1
   const int L = net.L;
 
-  // ---- the lane's point (both waves of a pair own the same 64 points) ----
+  // ---- the lane's point (the four waves of a tile own the same 64 points) ----
   float x = 0.f, t = 0.f;
   bool valid = false;
   int64_t p = 0;
   if (kind == 0) {
-    p = (int64_t)wg * kPtsPerWG + pair * 64 + lane;
+    p = (int64_t)wg * kPtsPerWG + trip * 64 + lane;
     valid = p < inst.n_r;
     if (valid) {
       x = inst.xt_r[2 * p];
       t = inst.xt_r[2 * p + 1];
     }
   } else if (kind == 1) {
-    p = (int64_t)wg * kPtsPerWG + pair * 64 + lane;
+    p = (int64_t)wg * kPtsPerWG + trip * 64 + lane;
     valid = p < inst.n_0;
     if (valid) x = inst.x_0[p];
   } else {
-    p = (int64_t)wg * kBcPairsPerWG + pair * 32 + (lane >> 1);
+    p = (int64_t)wg * kBcPairsPerWG + trip * 32 + (lane >> 1);
     valid = p < inst.n_b;
     x = (lane & 1) ? LRNR_TWO_PI_F : 0.f;
     if (valid) t = inst.t_b[p];
   }
-  float* ckbase = tile.ck + pair * ckpt_per_wave;
-  float* xb = sm.xbuf + pair * 2 * kSlotFloats;
+  float* ckbase = tile.ck + trip * ckpt_per_wave;
+  float* xa = sm.xa + trip * 2 * kXFloats;
+  float* xz = sm.xz + trip * 2 * kXFloats;
+  float* xg = sm.xg + trip * 2 * kXFloats;
   float amax = 0.f;
-
-  // ---- forward sweep --------------------------------------------------------
+  // M1: s * y^l;  M2: y^{l+1} (forward), ybar^{l+1} (reverse);  S1: wbar (reverse)
   f4 y[NJ][RGM];
+
+  // ---- forward sweep ----------------------------------------------------------
   for (int l = 1; l <= L - 1; ++l) {
     const bool first = l == 1, last = l == L - 1;
     const int KI = first ? 4 : RP, KO = last ? 4 : RP;
-    const int G = ((net.M[l] + 3) & ~3) / 4;
+    const int Gs = (((net.M[l] + 3) & ~3) / 4 + NG - 1) / NG;
     __syncthreads();
     stage_layer<kWsThreads>(net, s, l, KI, KO, sm.Us, sm.Vs, sm.bs, sm.ss);
     __syncthreads();
-    if (isM) {
+    if (role == 0) {
       if (first)
         input_jets<NJ, RGM>(net, x, t, y);
       else
         ckpt_load<NJ, RGM>(ckbase + (l - 2) * kSlot, lane, y);
+      const int RGI = first ? 1 : RGM;
+#pragma unroll
+      for (int g = 0; g < RGM; ++g) {
+        if (g < RGI) {
+          const f4 s4 = *reinterpret_cast<const f4*>(sm.ss + 4 * g);
+#pragma unroll
+          for (int c = 0; c < NJ; ++c) y[c][g] *= s4;
+        }
+      }
       if (first)
-        ws_fwd_M<NJ, RGM, 1>(sm, xb, G, li, lane, y);
+        m1_loop<NJ, RGM, 1, NG>(sm, xa, Gs, Gs + 2, li, lane, y);
       else
-        ws_fwd_M<NJ, RGM, RGM>(sm, xb, G, li, lane, y);
+        m1_loop<NJ, RGM, RGM, NG>(sm, xa, Gs, Gs + 2, li, lane, y);
+    } else if (role >= 2) {
+      s_fwd_loop<NJ, NG>(xa, xz, Gs, lane, role - 2, amax);
     } else {
+#pragma unroll
+      for (int c = 0; c < NJ; ++c)
+#pragma unroll
+        for (int g = 0; g < RGM; ++g) y[c][g] = zero4();
       if (last)
-        ws_fwd_E<NJ, RGM, 1>(sm, xb, G, li, lane, y, amax);
+        m2_fwd_loop<NJ, RGM, 1, NG>(sm, xz, Gs, li, lane, y);
       else
-        ws_fwd_E<NJ, RGM, RGM>(sm, xb, G, li, lane, y, amax);
+        m2_fwd_loop<NJ, RGM, RGM, NG>(sm, xz, Gs, li, lane, y);
       if (!last) ckpt_store<NJ, RGM>(ckbase + (l - 1) * kSlot, lane, y);
     }
   }
 
-  // ---- output layer, residual and loss adjoints (E waves) ----------------
+  // ---- output layer, residual and loss adjoints (M2) --------------------------
   const float UL = net.U[net.offU[L]];
   const float sL = s[net.offS[L]];
   const float bL = net.b[net.offB[L]];
   const float cL = UL * sL;
   const int comp = sum4_component(lane);
-  if (!isM) {
+  if (role == 1) {
     float u[NJ];
 #pragma unroll
     for (int c = 0; c < NJ; ++c) u[c] = cL * y[c][0][0];
@@ -285,31 +500,22 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
 #pragma unroll
     for (int c = 0; c < NJ; ++c) sLb += ub[c] * y[c][0][0];
     const float tot = wave_sum4(f4{lsum, UL * sLb, ub[0], 0.f}, lane);
-    if ((lane & 15) == 0) sm.lw[pair * 4 + comp] = tot;
-    f4 ybL[NJ];
+    if ((lane & 15) == 0) sm.lw[trip * 4 + comp] = tot;
+    // ybar^L for the reverse sweep of the last hidden layer
 #pragma unroll
-    for (int c = 0; c < NJ; ++c) ybL[c] = f4{cL * ub[c], 0.f, 0.f, 0.f};
-    xput<NJ>(xb, lane, ybL);
+    for (int c = 0; c < NJ; ++c) {
+#pragma unroll
+      for (int g = 0; g < RGM; ++g) y[c][g] = zero4();
+      y[c][0] = f4{cL * ub[c], 0.f, 0.f, 0.f};
+    }
   }
-  __syncthreads();
 
-  // ---- reverse sweep --------------------------------------------------------
+  // ---- reverse sweep -----------------------------------------------------------
   float* rec = tile.rec;
-  f4 yb[NJ][RGM];  // M: ybar^{l+1};  E: wbar of the current layer
-  if (isM) {
-#pragma unroll
-    for (int c = 0; c < NJ; ++c)
-#pragma unroll
-      for (int g = 0; g < RGM; ++g) yb[c][g] = zero4();
-    f4 ybL[NJ];
-    xget<NJ>(xb, lane, ybL);
-#pragma unroll
-    for (int c = 0; c < NJ; ++c) yb[c][0] = ybL[c];
-  }
   for (int l = L - 1; l >= 1; --l) {
     const bool first = l == 1, last = l == L - 1;
     const int KI = first ? 4 : RP, KO = last ? 4 : RP;
-    const int G = ((net.M[l] + 3) & ~3) / 4;
+    const int Gs = (((net.M[l] + 3) & ~3) / 4 + NG - 1) / NG;
     __syncthreads();
     if (l == L - 1 && tid < 4) {
       const float v = ((sm.lw[tid] + sm.lw[4 + tid]) + sm.lw[8 + tid]) + sm.lw[12 + tid];
@@ -326,55 +532,66 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
     }
     stage_layer<kWsThreads>(net, s, l, KI, KO, sm.Us, sm.Vs, sm.bs, sm.ss);
     __syncthreads();
-    if (isM) {
-      f4 ys[NJ][RGM];
+    if (role == 0) {
       if (first)
-        input_jets<NJ, RGM>(net, x, t, ys);
+        input_jets<NJ, RGM>(net, x, t, y);
       else
-        ckpt_load<NJ, RGM>(ckbase + (l - 2) * kSlot, lane, ys);
-      // ybar^{l+1} was left in slot l by the E wave at the end of layer l+1
-      if (!last) ckpt_load<NJ, RGM>(ckbase + l * kSlot, lane, yb);
-      if (first && last)
-        ws_bwd_M<NJ, RGM, 1, 1>(sm, xb, G, li, lane, ys, yb);
-      else if (first)
-        ws_bwd_M<NJ, RGM, 1, RGM>(sm, xb, G, li, lane, ys, yb);
-      else if (last)
-        ws_bwd_M<NJ, RGM, RGM, 1>(sm, xb, G, li, lane, ys, yb);
-      else
-        ws_bwd_M<NJ, RGM, RGM, RGM>(sm, xb, G, li, lane, ys, yb);
-    } else {
-      float* brow = sm.bbar + pair * Wmax_p;
-      if (first)
-        ws_bwd_E<NJ, RGM, 1>(sm, xb, G, li, lane, yb, brow, amax);
-      else
-        ws_bwd_E<NJ, RGM, RGM>(sm, xb, G, li, lane, yb, brow, amax);
-      // dL/ds^l = sum_c wbar_c * y_c, and ybar^l = s * wbar for the layer below
-      f4 yl[NJ][RGM];
-      if (first)
-        input_jets<NJ, RGM>(net, x, t, yl);
-      else
-        ckpt_load<NJ, RGM>(ckbase + (l - 2) * kSlot, lane, yl);
+        ckpt_load<NJ, RGM>(ckbase + (l - 2) * kSlot, lane, y);
       const int RGI = first ? 1 : RGM;
 #pragma unroll
       for (int g = 0; g < RGM; ++g) {
         if (g < RGI) {
-          f4 acc = zero4();
-#pragma unroll
-          for (int c = 0; c < NJ; ++c) acc += yb[c][g] * yl[c][g];
-          const float tot = wave_sum4(acc, lane);
-          if ((lane & 15) == 0) sm.sbar[pair * RP + 4 * g + comp] = tot;
-        }
-      }
-      if (!first) {
-#pragma unroll
-        for (int g = 0; g < RGM; ++g) {
           const f4 s4 = *reinterpret_cast<const f4*>(sm.ss + 4 * g);
 #pragma unroll
-          for (int c = 0; c < NJ; ++c) yl[c][g] = s4 * yb[c][g];
+          for (int c = 0; c < NJ; ++c) y[c][g] *= s4;
         }
-        // ybar^l goes to slot l-1 (y^{l+1} there is no longer needed)
-        ckpt_store<NJ, RGM>(ckbase + (l - 1) * kSlot, lane, yl);
       }
+      if (first)
+        m1_loop<NJ, RGM, 1, NG>(sm, xa, Gs, Gs + 2, li, lane, y);
+      else
+        m1_loop<NJ, RGM, RGM, NG>(sm, xa, Gs, Gs + 2, li, lane, y);
+    } else if (role == 1) {
+      // ybar^{l+1} was left in slot l by S1 at the end of layer l+1
+      if (!last) ckpt_load<NJ, RGM>(ckbase + l * kSlot, lane, y);
+      if (last)
+        m2_bwd_loop<NJ, RGM, 1, NG>(sm, xz, Gs, li, lane, y);
+      else
+        m2_bwd_loop<NJ, RGM, RGM, NG>(sm, xz, Gs, li, lane, y);
+    } else if (role == 2) {
+      s0_bwd_loop<NJ, NG>(xa, xz, xg, Gs, lane, sm.bbar + trip * Wmax_p, amax);
+    } else {
+#pragma unroll
+      for (int c = 0; c < NJ; ++c)
+#pragma unroll
+        for (int g = 0; g < RGM; ++g) y[c][g] = zero4();
+      if (first)
+        s1_bwd_loop<NJ, RGM, 1, NG>(sm, xg, Gs, li, lane, y);
+      else
+        s1_bwd_loop<NJ, RGM, RGM, NG>(sm, xg, Gs, li, lane, y);
+      // dL/ds^l = sum_c wbar_c * y_c^l and ybar^l = s * wbar, one rank group at a time
+      const int RGI = first ? 1 : RGM;
+#pragma unroll
+      for (int g = 0; g < RGM; ++g) {
+        if (g < RGI) {
+          f4 yl[NJ];
+          if (first)
+            input_jets_g0<NJ>(net, x, t, yl);
+          else
+            ckpt_load_g<NJ, RGM>(ckbase + (l - 2) * kSlot, lane, g, yl);
+          f4 acc = zero4();
+#pragma unroll
+          for (int c = 0; c < NJ; ++c) acc += y[c][g] * yl[c];
+          const float tot = wave_sum4(acc, lane);
+          if ((lane & 15) == 0) sm.sbar[trip * RP + 4 * g + comp] = tot;
+          if (!first) {
+            const f4 s4 = *reinterpret_cast<const f4*>(sm.ss + 4 * g);
+#pragma unroll
+            for (int c = 0; c < NJ; ++c) y[c][g] = s4 * y[c][g];
+          }
+        }
+      }
+      // ybar^l goes to slot l-1 (y^{l+1} there is no longer needed)
+      if (!first) ckpt_store<NJ, RGM>(ckbase + (l - 1) * kSlot, lane, y);
     }
     __syncthreads();
     const int W = net.M[l], rl = net.r[l], Wm = Wmax_p;
@@ -385,30 +602,16 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
       rec[4 + net.offS[l] + i] =
           ((sm.sbar[i] + sm.sbar[RP + i]) + sm.sbar[2 * RP + i]) + sm.sbar[3 * RP + i];
   }
-  // flag the workgroup for the accurate relaunch if any lane met |a| > kFastRange
+  // flag the tile for the accurate relaunch if any lane met |a| > kFastRange
   const bool bad = __any(!(amax <= kFastRange));
   __syncthreads();
-  if (lane == 0) sm.lw[wave] = bad ? 1.f : 0.f;
+  if (lane == 0) sm.lw[16 + wave] = bad ? 1.f : 0.f;
   __syncthreads();
   if (tid == 0) {
     float any = 0.f;
-    for (int w = 0; w < kWsWaves; ++w) any += sm.lw[w];
+    for (int w = 0; w < kWsWaves; ++w) any += sm.lw[16 + w];
     *tile.flag = any > 0.f ? 1 : 0;
   }
-}
-
-// LDS carve-up of the wave-specialised kernels.
-__device__ __forceinline__ SmemWS ws_smem(float* base, int Wm, int RP) {
-  SmemWS sm;
-  sm.Us = base;
-  sm.Vs = sm.Us + Wm * RP;
-  sm.bs = sm.Vs + Wm * RP;
-  sm.ss = sm.bs + Wm;
-  sm.xbuf = sm.ss + RP;
-  sm.bbar = sm.xbuf + 4 * 2 * kSlotFloats;
-  sm.sbar = sm.bbar + 4 * Wm;
-  sm.lw = sm.sbar + 4 * RP;
-  return sm;
 }
 
 template <int RP>
@@ -439,22 +642,10 @@ __global__ __launch_bounds__(kWsThreads) void lrnr_grad_ws_kernel(KNet net, KIns
     ws_run<RP, 1, false>(net, inst, grid.ckpt_per_wave, grid.Wmax_p, tile, kind, wg, s, mu, sm);
 }
 
-template <int RP>
-hipError_t launch_grad_ws(const KNet& net, const KInst& inst, const KGrid& grid,
-                          hipStream_t stream) {
-  const dim3 blocks((unsigned)(grid.B * grid.G_inst)), threads(kWsThreads);
-  const size_t lds = ws_lds_floats(RP, grid.Wmax_p) * sizeof(float);
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)lrnr_grad_ws_kernel<RP>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL((lrnr_grad_ws_kernel<RP>), blocks, threads, lds, stream, net, inst, grid);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  // workgroups that met |a| > kFastRange are recomputed with ocml's sin/cos
-  return launch_one<RP, MODE_GRAD, SC_ACC>(net, inst, grid, stream);
-}
+// Rank tiles above this run the single-role kernel for the reverse modes:
+// four jets of 24 or 32 ranks per role do not fit four waves per SIMD (at
+// rank 20 a few long-lived values are spilled outside the MFMA loops).
+constexpr int kWsMaxRP = 20;
 
 // ---------------------------------------------------------------------------
 // Task-table launches: a persistent grid strides over the tiles of all tasks.
@@ -599,9 +790,17 @@ static int resident_grid(K kernel, int threads, size_t lds) {
 template <int RP>
 int table_grid_rp(int mode, int Wmax_p) {
   if (reverse_mode(mode)) {
-    const size_t lds = ws_lds_floats(RP, Wmax_p) * sizeof(float);
-    return mode == MODE_VJP ? resident_grid(lrnr_grad_ws_table_kernel<RP, true>, kWsThreads, lds)
-                            : resident_grid(lrnr_grad_ws_table_kernel<RP, false>, kWsThreads, lds);
+    if constexpr (RP > kWsMaxRP) {
+      const size_t lds = fused_lds_bytes(RP, Wmax_p);
+      return mode == MODE_VJP
+                 ? resident_grid(lrnr_table_kernel<RP, MODE_VJP, SC_TRACK>, kThreads, lds)
+                 : resident_grid(lrnr_table_kernel<RP, MODE_GRAD, SC_TRACK>, kThreads, lds);
+    } else {
+      const size_t lds = ws_lds_floats(RP, Wmax_p) * sizeof(float);
+      return mode == MODE_VJP
+                 ? resident_grid(lrnr_grad_ws_table_kernel<RP, true>, kWsThreads, lds)
+                 : resident_grid(lrnr_grad_ws_table_kernel<RP, false>, kWsThreads, lds);
+    }
   }
   const size_t lds = fused_lds_bytes(RP, Wmax_p);
   switch (mode) {
@@ -624,15 +823,22 @@ static hipError_t launch_table_one(const KTableGrid& tg, int grid, hipStream_t s
 
 template <int RP, bool VJP>
 static hipError_t launch_table_rev(const KTableGrid& tg, int grid, hipStream_t stream) {
-  const size_t lds = ws_lds_floats(RP, tg.Wmax_p) * sizeof(float);
-  hipError_t e = set_lds(lrnr_grad_ws_table_kernel<RP, VJP>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((lrnr_grad_ws_table_kernel<RP, VJP>), dim3(grid), dim3(kWsThreads), lds,
-                     stream, tg);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  // tiles that met |a| > kFastRange are recomputed with ocml's sin/cos
-  return launch_table_one<RP, VJP ? MODE_VJP : MODE_GRAD, SC_ACC>(tg, grid, stream);
+  constexpr int MODE = VJP ? MODE_VJP : MODE_GRAD;
+  if constexpr (RP > kWsMaxRP) {
+    hipError_t e = launch_table_one<RP, MODE, SC_TRACK>(tg, grid, stream);
+    if (e != hipSuccess) return e;
+    return launch_table_one<RP, MODE, SC_ACC>(tg, grid, stream);
+  } else {
+    const size_t lds = ws_lds_floats(RP, tg.Wmax_p) * sizeof(float);
+    hipError_t e = set_lds(lrnr_grad_ws_table_kernel<RP, VJP>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((lrnr_grad_ws_table_kernel<RP, VJP>), dim3(grid), dim3(kWsThreads), lds,
+                       stream, tg);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // tiles that met |a| > kFastRange are recomputed with ocml's sin/cos
+    return launch_table_one<RP, MODE, SC_ACC>(tg, grid, stream);
+  }
 }
 
 // grid: persistent workgroups; the checkpoint slab holds grid * kWaves slabs.
@@ -644,6 +850,26 @@ hipError_t launch_table_rp(int mode, const KTableGrid& tg, int grid, hipStream_t
     case MODE_LOSS: return launch_table_one<RP, MODE_LOSS, SC_REDO>(tg, grid, stream);
     case MODE_VJP: return launch_table_rev<RP, true>(tg, grid, stream);
     default: return launch_table_rev<RP, false>(tg, grid, stream);
+  }
+}
+
+template <int RP>
+hipError_t launch_grad_ws(const KNet& net, const KInst& inst, const KGrid& grid,
+                          hipStream_t stream) {
+  if constexpr (RP > kWsMaxRP) {
+    hipError_t e = launch_one<RP, MODE_GRAD, SC_TRACK>(net, inst, grid, stream);
+    if (e != hipSuccess) return e;
+    return launch_one<RP, MODE_GRAD, SC_ACC>(net, inst, grid, stream);
+  } else {
+    const dim3 blocks((unsigned)(grid.B * grid.G_inst)), threads(kWsThreads);
+    const size_t lds = ws_lds_floats(RP, grid.Wmax_p) * sizeof(float);
+    hipError_t e = set_lds(lrnr_grad_ws_kernel<RP>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((lrnr_grad_ws_kernel<RP>), blocks, threads, lds, stream, net, inst, grid);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // workgroups that met |a| > kFastRange are recomputed with ocml's sin/cos
+    return launch_one<RP, MODE_GRAD, SC_ACC>(net, inst, grid, stream);
   }
 }
 
