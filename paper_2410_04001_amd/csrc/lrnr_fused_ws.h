@@ -168,6 +168,51 @@ __device__ __forceinline__ void rows_times(const float* __restrict__ R,
   }
 }
 
+// rows_times for NG consecutive groups w0, w0+4, ... at once: out[q * NJ + c]
+// is jet c of group q.  The NG x NJ accumulator chains are interleaved, which
+// keeps the one-jet (value-only) tiles from waiting on a single dependent
+// MFMA chain; for NG = 1 this is rows_times.
+template <int NJ, int RGM, int RG, bool BIAS, int NG, int KLAST = 4>
+__device__ __forceinline__ void rows_times_ng(const float* __restrict__ R,
+                                              const float* __restrict__ bs, int w0, int li,
+                                              const f4 (&y)[NJ][RGM], f4 (&out)[NJ * NG]) {
+  constexpr int K = 4 * RG;
+  f4 nxt[NG];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    if constexpr (BIAS)
+      out[q * NJ] = *reinterpret_cast<const f4*>(bs + w0 + 4 * q);
+    else
+      out[q * NJ] = zero4();
+#pragma unroll
+    for (int c = 1; c < NJ; ++c) out[q * NJ + c] = zero4();
+    nxt[q] = *reinterpret_cast<const f4*>(R + (w0 + 4 * q + li) * K);
+  }
+#pragma unroll
+  for (int g = 0; g < RG; ++g) {
+    f4 cur[NG];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) cur[q] = nxt[q];
+    if (g + 1 < RG) {
+#pragma unroll
+      for (int q = 0; q < NG; ++q)
+        nxt[q] = *reinterpret_cast<const f4*>(R + (w0 + 4 * q + li) * K + 4 * (g + 1));
+    }
+    // the last rank group may be zero-padded beyond KLAST (the input layer:
+    // r_1 <= 2 because (x, t) has two components)
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      if (g < RG - 1 || kk < KLAST) {
+#pragma unroll
+        for (int q = 0; q < NG; ++q)
+#pragma unroll
+          for (int c = 0; c < NJ; ++c)
+            out[q * NJ + c] = mfma4(cur[q][kk], y[c][g][kk], out[q * NJ + c]);
+      }
+    }
+  }
+}
+
 // acc += R[w0..w0+3]^T v: R row-major [W][4 RG], v per neuron (f4 of 4 neurons)
 template <int NJ, int RGM, int RG>
 __device__ __forceinline__ void rows_t_times(const float* __restrict__ R, int w0, int li,
@@ -202,19 +247,13 @@ __device__ __forceinline__ void rows_t_times(const float* __restrict__ R, int w0
 // ---------------------------------------------------------------------------
 
 // M1: a = U (s y) + b for block k (both sweeps)
-template <int NJ, int RGM, int RGI, int NG>
+template <int NJ, int RGM, int RGI, int NG, int KLAST = 4>
 __device__ __forceinline__ void m1_loop(const SmemWS& sm, float* xa, int Gs, int steps, int li,
                                         int lane, const f4 (&ys)[NJ][RGM]) {
   for (int k = 0; k < steps; ++k) {
     if (k < Gs) {
       f4 a[NJ * NG];
-#pragma unroll
-      for (int q = 0; q < NG; ++q) {
-        f4 aq[NJ];
-        rows_times<NJ, RGM, RGI, true>(sm.Us, sm.bs, 4 * (k * NG + q), li, ys, aq);
-#pragma unroll
-        for (int c = 0; c < NJ; ++c) a[q * NJ + c] = aq[c];
-      }
+      rows_times_ng<NJ, RGM, RGI, true, NG, KLAST>(sm.Us, sm.bs, 4 * k * NG, li, ys, a);
       xput<NJ * NG>(xa + (k & 1) * kXFloats, lane, a);
     }
     __syncthreads();
@@ -271,13 +310,7 @@ __device__ __forceinline__ void m2_bwd_loop(const SmemWS& sm, float* xz, int Gs,
   for (int k = 0; k < Gs + 2; ++k) {
     if (k < Gs) {
       f4 zb[NJ * NG];
-#pragma unroll
-      for (int q = 0; q < NG; ++q) {
-        f4 zq[NJ];
-        rows_times<NJ, RGM, RGO, false>(sm.Vs, nullptr, 4 * (k * NG + q), li, yb, zq);
-#pragma unroll
-        for (int c = 0; c < NJ; ++c) zb[q * NJ + c] = zq[c];
-      }
+      rows_times_ng<NJ, RGM, RGO, false, NG>(sm.Vs, nullptr, 4 * k * NG, li, yb, zb);
       xput<NJ * NG>(xz + (k & 1) * kXFloats, lane, zb);
     }
     __syncthreads();
@@ -429,7 +462,7 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
         }
       }
       if (first)
-        m1_loop<NJ, RGM, 1, NG>(sm, xa, Gs, Gs + 2, li, lane, y);
+        m1_loop<NJ, RGM, 1, NG, 2>(sm, xa, Gs, Gs + 2, li, lane, y);
       else
         m1_loop<NJ, RGM, RGM, NG>(sm, xa, Gs, Gs + 2, li, lane, y);
     } else if (role >= 2) {
@@ -547,7 +580,7 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
         }
       }
       if (first)
-        m1_loop<NJ, RGM, 1, NG>(sm, xa, Gs, Gs + 2, li, lane, y);
+        m1_loop<NJ, RGM, 1, NG, 2>(sm, xa, Gs, Gs + 2, li, lane, y);
       else
         m1_loop<NJ, RGM, RGM, NG>(sm, xa, Gs, Gs + 2, li, lane, y);
     } else if (role == 1) {
