@@ -40,6 +40,7 @@ namespace lrnr {
 constexpr int kWsWaves = 16;
 constexpr int kWsThreads = 64 * kWsWaves;
 constexpr int kXFloats = 4 * 64 * 4;   // one exchange slot: 4 f4 per lane
+constexpr int kMaxCols = 2;            // value points per lane of a value-only tile
 
 typedef float f2 __attribute__((ext_vector_type(2)));
 
@@ -51,14 +52,14 @@ struct SmemWS {
   float* xa;    // [4 tiles][2 slots][kXFloats]  a                     (M1 -> S)
   float* xz;    // [4 tiles][2 slots][kXFloats]  z (S -> M2) / zbar (M2 -> S0)
   float* xg;    // [4 tiles][2 slots][kXFloats]  abar                  (S0 -> S1)
-  float* bbar;  // [4][Wmax_p]
-  float* sbar;  // [4][RP]
-  float* lw;    // [16] loss sums, [16] range flags
+  float* bbar;  // [kMaxCols][4][Wmax_p]
+  float* sbar;  // [kMaxCols][4][RP]
+  float* lw;    // [kMaxCols][16] loss sums, [16] range flags
 };
 
 inline size_t ws_lds_floats(int RP, int Wmax_p) {
   return (size_t)Wmax_p * RP * 2 + Wmax_p + RP + (size_t)3 * 4 * 2 * kXFloats +
-         (size_t)4 * Wmax_p + (size_t)4 * RP + 32;
+         (size_t)kMaxCols * 4 * (Wmax_p + RP) + 16 * (kMaxCols + 1);
 }
 
 __device__ __forceinline__ SmemWS ws_smem(float* base, int Wm, int RP) {
@@ -71,8 +72,8 @@ __device__ __forceinline__ SmemWS ws_smem(float* base, int Wm, int RP) {
   sm.xz = sm.xa + 4 * 2 * kXFloats;
   sm.xg = sm.xz + 4 * 2 * kXFloats;
   sm.bbar = sm.xg + 4 * 2 * kXFloats;
-  sm.sbar = sm.bbar + 4 * Wm;
-  sm.lw = sm.sbar + 4 * RP;
+  sm.sbar = sm.bbar + kMaxCols * 4 * Wm;
+  sm.lw = sm.sbar + kMaxCols * 4 * RP;
   return sm;
 }
 
@@ -137,6 +138,65 @@ __device__ __forceinline__ void sigma_fwd2(const f2 (&a)[NJ], f2 (&z)[NJ], float
   }
 }
 
+// sin of N pairs of pre-activations of value-only columns (independent
+// points, no derivative jets), with one wave-uniform range test for all
+template <int N>
+__device__ __forceinline__ void sigma_fwd_vals(const f2 (&a)[N], f2 (&z)[N], float& amax) {
+  float m = 0.f;
+#pragma unroll
+  for (int i = 0; i < N; ++i) m = fmaxf(m, fmaxf(fabsf(a[i][0]), fabsf(a[i][1])));
+  amax = fmaxf(amax, m);
+  if (__all(m <= kHwRange)) {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        float sj, cj;
+        sincos_hw(a[i][j], sj, cj);
+        z[i][j] = sj;
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        float sj, cj;
+        sincos_fast(a[i][j], sj, cj);
+        z[i][j] = sj;
+      }
+  }
+}
+
+// adjoint of sigma_fwd_vals: abar = cos(a) zbar
+template <int N>
+__device__ __forceinline__ void sigma_bwd_vals(const f4 (&a)[N], const f4 (&zb)[N], f4 (&ab)[N],
+                                               float& amax) {
+  float m = 0.f;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    m = fmaxf(m, fmaxf(fmaxf(fabsf(a[i][0]), fabsf(a[i][1])), fmaxf(fabsf(a[i][2]), fabsf(a[i][3]))));
+  amax = fmaxf(amax, m);
+  if (__all(m <= kHwRange)) {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float sj, cj;
+        sincos_hw(a[i][j], sj, cj);
+        ab[i][j] = cj * zb[i][j];
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float sj, cj;
+        sincos_fast(a[i][j], sj, cj);
+        ab[i][j] = cj * zb[i][j];
+      }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Contractions of one 4-neuron group with the factor entries read from LDS
 // one rank group (or one neuron) ahead of the MFMAs that use them, which keeps
@@ -180,12 +240,12 @@ __device__ __forceinline__ void rows_times_ng(const float* __restrict__ R,
   f4 nxt[NG];
 #pragma unroll
   for (int q = 0; q < NG; ++q) {
-    if constexpr (BIAS)
-      out[q * NJ] = *reinterpret_cast<const f4*>(bs + w0 + 4 * q);
-    else
-      out[q * NJ] = zero4();
+    f4 bias = zero4();
+    if constexpr (BIAS) bias = *reinterpret_cast<const f4*>(bs + w0 + 4 * q);
+    out[q * NJ] = bias;
+    // four jets: the bias enters the value jet only; value columns: every one
 #pragma unroll
-    for (int c = 1; c < NJ; ++c) out[q * NJ + c] = zero4();
+    for (int c = 1; c < NJ; ++c) out[q * NJ + c] = NJ == 4 ? zero4() : bias;
     nxt[q] = *reinterpret_cast<const f4*>(R + (w0 + 4 * q + li) * K);
   }
 #pragma unroll
@@ -268,14 +328,18 @@ __device__ __forceinline__ void s_fwd_loop(const float* xa, float* xz, int Gs, i
     if (k >= 1 && k <= Gs) {
       f2 a[NJ * NG], z[NJ * NG];
       xget2<NJ * NG>(xa + ((k - 1) & 1) * kXFloats, lane, h, a);
+      if constexpr (NJ == 4) {
 #pragma unroll
-      for (int q = 0; q < NG; ++q) {
-        f2 aq[NJ], zq[NJ];
+        for (int q = 0; q < NG; ++q) {
+          f2 aq[NJ], zq[NJ];
 #pragma unroll
-        for (int c = 0; c < NJ; ++c) aq[c] = a[q * NJ + c];
-        sigma_fwd2<NJ>(aq, zq, amax);
+          for (int c = 0; c < NJ; ++c) aq[c] = a[q * NJ + c];
+          sigma_fwd2<NJ>(aq, zq, amax);
 #pragma unroll
-        for (int c = 0; c < NJ; ++c) z[q * NJ + c] = zq[c];
+          for (int c = 0; c < NJ; ++c) z[q * NJ + c] = zq[c];
+        }
+      } else {
+        sigma_fwd_vals<NJ * NG>(a, z, amax);
       }
       xput2<NJ * NG>(xz + ((k - 1) & 1) * kXFloats, lane, h, z);
     }
@@ -318,10 +382,11 @@ __device__ __forceinline__ void m2_bwd_loop(const SmemWS& sm, float* xz, int Gs,
 }
 
 // S0 reverse: adjoint of the sin jets and the db row for block k - 1
+// (bbar_row + c * col_stride is the db row of value column c)
 template <int NJ, int NG>
 __device__ __forceinline__ void s0_bwd_loop(const float* xa, const float* xz, float* xg, int Gs,
                                             int lane, float* __restrict__ bbar_row,
-                                            float& amax) {
+                                            int col_stride, float& amax) {
   const int comp = sum4_component(lane);
   for (int k = 0; k < Gs + 2; ++k) {
     if (k >= 1 && k <= Gs) {
@@ -329,24 +394,32 @@ __device__ __forceinline__ void s0_bwd_loop(const float* xa, const float* xz, fl
       f4 a[NJ * NG], zb[NJ * NG], ab[NJ * NG];
       xget<NJ * NG>(xa + slot, lane, a);
       xget<NJ * NG>(xz + slot, lane, zb);
+      if constexpr (NJ == 4) {
 #pragma unroll
-      for (int q = 0; q < NG; ++q) {
-        f4 aq[NJ], zq[NJ], gq[NJ];
+        for (int q = 0; q < NG; ++q) {
+          f4 aq[NJ], zq[NJ], gq[NJ];
 #pragma unroll
-        for (int c = 0; c < NJ; ++c) {
-          aq[c] = a[q * NJ + c];
-          zq[c] = zb[q * NJ + c];
+          for (int c = 0; c < NJ; ++c) {
+            aq[c] = a[q * NJ + c];
+            zq[c] = zb[q * NJ + c];
+          }
+          sigma_bwd<NJ, false>(aq, zq, gq, amax);
+#pragma unroll
+          for (int c = 0; c < NJ; ++c) ab[q * NJ + c] = gq[c];
         }
-        sigma_bwd<NJ, false>(aq, zq, gq, amax);
-#pragma unroll
-        for (int c = 0; c < NJ; ++c) ab[q * NJ + c] = gq[c];
+      } else {
+        sigma_bwd_vals<NJ * NG>(a, zb, ab, amax);
       }
       xput<NJ * NG>(xg + slot, lane, ab);
+      // db: the value jet of a four-jet tile; every column of a value tile
+      constexpr int NB = NJ == 4 ? 1 : NJ;
 #pragma unroll
-      for (int q = 0; q < NG; ++q) {
-        const float bsum = wave_sum4(ab[q * NJ], lane);
-        if ((lane & 15) == 0) bbar_row[4 * ((k - 1) * NG + q) + comp] = bsum;
-      }
+      for (int q = 0; q < NG; ++q)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          const float bsum = wave_sum4(ab[q * NJ + c], lane);
+          if ((lane & 15) == 0) bbar_row[c * col_stride + 4 * ((k - 1) * NG + q) + comp] = bsum;
+        }
     }
     __syncthreads();
   }
@@ -396,42 +469,88 @@ __device__ __forceinline__ void input_jets_g0(const KNet& net, float x, float t,
   }
 }
 
+// y^1 = V^1T (x, t) of NC independent points (value-only columns).
+template <int NC, int RGM>
+__device__ __forceinline__ void input_vals(const KNet& net, const float (&x)[NC],
+                                           const float (&t)[NC], f4 (&y)[NC][RGM]) {
+  const int r1 = net.r[1];
+  const float* V1 = net.V + net.offV[1];
+  const float v00 = V1[0], v10 = V1[r1];
+  const float v01 = r1 > 1 ? V1[1] : 0.f, v11 = r1 > 1 ? V1[r1 + 1] : 0.f;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+#pragma unroll
+    for (int g = 0; g < RGM; ++g) y[c][g] = zero4();
+    y[c][0] = f4{v00 * x[c] + v10 * t[c], v01 * x[c] + v11 * t[c], 0.f, 0.f};
+  }
+}
+
+template <int NC>
+__device__ __forceinline__ void input_vals_g0(const KNet& net, const float (&x)[NC],
+                                              const float (&t)[NC], f4 (&y)[NC]) {
+  const int r1 = net.r[1];
+  const float* V1 = net.V + net.offV[1];
+  const float v00 = V1[0], v10 = V1[r1];
+  const float v01 = r1 > 1 ? V1[1] : 0.f, v11 = r1 > 1 ? V1[r1 + 1] : 0.f;
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    y[c] = f4{v00 * x[c] + v10 * t[c], v01 * x[c] + v11 * t[c], 0.f, 0.f};
+}
+
 // ---------------------------------------------------------------------------
-// Workgroup driver (MODE_GRAD / MODE_VJP, fast sin/cos with range tracking)
+// Workgroup driver (MODE_GRAD / MODE_VJP, fast sin/cos with range tracking).
+//
+// NJ = 4: four-jet interior tile (one point per lane).  NJ < 4: value-only
+// IC/BC tiles with NJ independent points per lane ("columns"); column c of
+// workgroup wg covers tile NJ wg + c of its kind and reduces into that tile's
+// own record (tiles[c]), so records, flags and the accurate relaunch are the
+// same whatever the number of columns.  n_tiles is the number of tiles of
+// this kind (a trailing column beyond it writes nothing).
 // ---------------------------------------------------------------------------
 template <int RP, int NJ, bool VJP>
 __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave, int Wmax_p,
-                       const KTile& tile, int kind, int wg, const float* __restrict__ s,
-                       const float* __restrict__ mu, const SmemWS& sm) {
+                       const KTile* tiles, int kind, int wg, int n_tiles,
+                       const float* __restrict__ s, const float* __restrict__ mu,
+                       const SmemWS& sm) {
+  constexpr bool JET = NJ == 4;
+  constexpr int NC = JET ? 1 : NJ;              // points per lane
   constexpr int RGM = RP / 4;
   constexpr int NG = 4 / NJ;                    // 4-neuron groups per step
   constexpr int64_t kSlot = 4 * RGM * 64 * 4;  // floats per checkpoint slot
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 3;
   const int trip = wave & 3, role = wave >> 2;  // 0: M1, 1: M2, 2: S0, 3: S1
   const int L = net.L;
+  const int Wm = Wmax_p;
 
-  // ---- the lane's point (the four waves of a tile own the same 64 points) ----
-  float x = 0.f, t = 0.f;
-  bool valid = false;
-  int64_t p = 0;
-  if (kind == 0) {
-    p = (int64_t)wg * kPtsPerWG + trip * 64 + lane;
-    valid = p < inst.n_r;
-    if (valid) {
-      x = inst.xt_r[2 * p];
-      t = inst.xt_r[2 * p + 1];
+  // ---- the lane's points (the four waves of a tile own the same points) ----
+  float x[NC], t[NC];
+  bool valid[NC], tile_ok[NC];
+  int64_t p[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int u = wg * NC + c;
+    tile_ok[c] = u < n_tiles;
+    x[c] = 0.f;
+    t[c] = 0.f;
+    if (kind == 0) {
+      p[c] = (int64_t)u * kPtsPerWG + trip * 64 + lane;
+      valid[c] = p[c] < inst.n_r;
+      if (valid[c]) {
+        x[c] = inst.xt_r[2 * p[c]];
+        t[c] = inst.xt_r[2 * p[c] + 1];
+      }
+    } else if (kind == 1) {
+      p[c] = (int64_t)u * kPtsPerWG + trip * 64 + lane;
+      valid[c] = p[c] < inst.n_0;
+      if (valid[c]) x[c] = inst.x_0[p[c]];
+    } else {
+      p[c] = (int64_t)u * kBcPairsPerWG + trip * 32 + (lane >> 1);
+      valid[c] = p[c] < inst.n_b;
+      x[c] = (lane & 1) ? LRNR_TWO_PI_F : 0.f;
+      if (valid[c]) t[c] = inst.t_b[p[c]];
     }
-  } else if (kind == 1) {
-    p = (int64_t)wg * kPtsPerWG + trip * 64 + lane;
-    valid = p < inst.n_0;
-    if (valid) x = inst.x_0[p];
-  } else {
-    p = (int64_t)wg * kBcPairsPerWG + trip * 32 + (lane >> 1);
-    valid = p < inst.n_b;
-    x = (lane & 1) ? LRNR_TWO_PI_F : 0.f;
-    if (valid) t = inst.t_b[p];
   }
-  float* ckbase = tile.ck + trip * ckpt_per_wave;
+  float* ckbase = tiles[0].ck + trip * ckpt_per_wave;
   float* xa = sm.xa + trip * 2 * kXFloats;
   float* xz = sm.xz + trip * 2 * kXFloats;
   float* xg = sm.xg + trip * 2 * kXFloats;
@@ -448,10 +567,14 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
     stage_layer<kWsThreads>(net, s, l, KI, KO, sm.Us, sm.Vs, sm.bs, sm.ss);
     __syncthreads();
     if (role == 0) {
-      if (first)
-        input_jets<NJ, RGM>(net, x, t, y);
-      else
+      if (first) {
+        if constexpr (JET)
+          input_jets<NJ, RGM>(net, x[0], t[0], y);
+        else
+          input_vals<NC, RGM>(net, x, t, y);
+      } else {
         ckpt_load<NJ, RGM>(ckbase + (l - 2) * kSlot, lane, y);
+      }
       const int RGI = first ? 1 : RGM;
 #pragma unroll
       for (int g = 0; g < RGM; ++g) {
@@ -490,50 +613,71 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
     float u[NJ];
 #pragma unroll
     for (int c = 0; c < NJ; ++c) u[c] = cL * y[c][0][0];
-    u[0] += bL;
+    if constexpr (JET) {
+      u[0] += bL;
+    } else {
+#pragma unroll
+      for (int c = 0; c < NJ; ++c) u[c] += bL;
+    }
     const int form = inst.form;
-    float lsum = 0.f;
+    float lsum[NC];
     float ub[NJ];
 #pragma unroll
     for (int c = 0; c < NJ; ++c) ub[c] = 0.f;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) lsum[c] = 0.f;
     if constexpr (VJP) {
       // cotangent of the jets supplied by the caller (interior points only)
-      if (valid) {
+      if (valid[0]) {
         const int64_t n = inst.n_r;
 #pragma unroll
-        for (int c = 0; c < NJ; ++c) ub[c] = inst.cot[c * n + p];
+        for (int c = 0; c < NJ; ++c) ub[c] = inst.cot[c * n + p[0]];
       }
-    } else if constexpr (NJ == 4) {
+    } else if constexpr (JET) {
       const float beta = mu[0], nu = mu[1], rho = mu[2];
       const float res = u[2] + beta * u[1] - nu * u[3] - rho * u[0] * (1.f - u[0]);
       const float phi = form == 0 ? res * res : fabsf(res);
       const float dphi = form == 0 ? 2.f * res : (res > 0.f ? 1.f : (res < 0.f ? -1.f : 0.f));
-      const float g = valid ? inst.wr_n * dphi : 0.f;
-      lsum = valid ? phi : 0.f;
+      const float g = valid[0] ? inst.wr_n * dphi : 0.f;
+      lsum[0] = valid[0] ? phi : 0.f;
       ub[0] = -rho * (1.f - 2.f * u[0]) * g;
       ub[1] = beta * g;
       ub[2] = g;
       ub[3] = -nu * g;
     } else if (kind == 1) {
-      const float e0 = u[0] - sinf(x);
-      const float phi = form == 0 ? e0 * e0 : fabsf(e0);
-      const float dphi = form == 0 ? 2.f * e0 : (e0 > 0.f ? 1.f : (e0 < 0.f ? -1.f : 0.f));
-      lsum = valid ? phi : 0.f;
-      ub[0] = valid ? inst.w0_n * dphi : 0.f;
-    } else {
-      const float other = __shfl_xor(u[0], 1);
-      const bool right = lane & 1;
-      const float eb = right ? other - u[0] : u[0] - other;
-      const float phi = form == 0 ? eb * eb : fabsf(eb);
-      const float dphi = form == 0 ? 2.f * eb : (eb > 0.f ? 1.f : (eb < 0.f ? -1.f : 0.f));
-      lsum = (valid && !right) ? phi : 0.f;
-      ub[0] = valid ? (right ? -inst.wb_n : inst.wb_n) * dphi : 0.f;
-    }
-    float sLb = 0.f;
 #pragma unroll
-    for (int c = 0; c < NJ; ++c) sLb += ub[c] * y[c][0][0];
-    const float tot = wave_sum4(f4{lsum, UL * sLb, ub[0], 0.f}, lane);
-    if ((lane & 15) == 0) sm.lw[trip * 4 + comp] = tot;
+      for (int c = 0; c < NC; ++c) {
+        const float e0 = u[c] - sinf(x[c]);
+        const float phi = form == 0 ? e0 * e0 : fabsf(e0);
+        const float dphi = form == 0 ? 2.f * e0 : (e0 > 0.f ? 1.f : (e0 < 0.f ? -1.f : 0.f));
+        lsum[c] = valid[c] ? phi : 0.f;
+        ub[c] = valid[c] ? inst.w0_n * dphi : 0.f;
+      }
+    } else {
+      const bool right = lane & 1;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const float other = __shfl_xor(u[c], 1);
+        const float eb = right ? other - u[c] : u[c] - other;
+        const float phi = form == 0 ? eb * eb : fabsf(eb);
+        const float dphi = form == 0 ? 2.f * eb : (eb > 0.f ? 1.f : (eb < 0.f ? -1.f : 0.f));
+        lsum[c] = (valid[c] && !right) ? phi : 0.f;
+        ub[c] = valid[c] ? (right ? -inst.wb_n : inst.wb_n) * dphi : 0.f;
+      }
+    }
+    if constexpr (JET) {
+      float sLb = 0.f;
+#pragma unroll
+      for (int c = 0; c < NJ; ++c) sLb += ub[c] * y[c][0][0];
+      const float tot = wave_sum4(f4{lsum[0], UL * sLb, ub[0], 0.f}, lane);
+      if ((lane & 15) == 0) sm.lw[trip * 4 + comp] = tot;
+    } else {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const float tot = wave_sum4(f4{lsum[c], UL * (ub[c] * y[c][0][0]), ub[c], 0.f}, lane);
+        if ((lane & 15) == 0) sm.lw[16 * c + trip * 4 + comp] = tot;
+      }
+    }
     // ybar^L for the reverse sweep of the last hidden layer
 #pragma unroll
     for (int c = 0; c < NJ; ++c) {
@@ -544,32 +688,40 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
   }
 
   // ---- reverse sweep -----------------------------------------------------------
-  float* rec = tile.rec;
   for (int l = L - 1; l >= 1; --l) {
     const bool first = l == 1, last = l == L - 1;
     const int KI = first ? 4 : RP, KO = last ? 4 : RP;
     const int Gs = (((net.M[l] + 3) & ~3) / 4 + NG - 1) / NG;
     __syncthreads();
-    if (l == L - 1 && tid < 4) {
-      const float v = ((sm.lw[tid] + sm.lw[4 + tid]) + sm.lw[8 + tid]) + sm.lw[12 + tid];
-      if (tid == 0) {
-        rec[0] = kind == 0 ? v : 0.f;
-        rec[1] = kind == 1 ? v : 0.f;
-        rec[2] = kind == 2 ? v : 0.f;
-        rec[3] = 0.f;
-      } else if (tid == 1) {
-        rec[4 + net.offS[L]] = v;
-      } else if (tid == 2) {
-        rec[4 + net.r_total + net.offB[L]] = v;
+    if (l == L - 1 && tid < 4 * NC) {
+      const int c = tid >> 2, e = tid & 3;
+      const float* lw = sm.lw + 16 * c;
+      const float v = ((lw[e] + lw[4 + e]) + lw[8 + e]) + lw[12 + e];
+      float* rec = tiles[c].rec;
+      if (tile_ok[c]) {
+        if (e == 0) {
+          rec[0] = kind == 0 ? v : 0.f;
+          rec[1] = kind == 1 ? v : 0.f;
+          rec[2] = kind == 2 ? v : 0.f;
+          rec[3] = 0.f;
+        } else if (e == 1) {
+          rec[4 + net.offS[L]] = v;
+        } else if (e == 2) {
+          rec[4 + net.r_total + net.offB[L]] = v;
+        }
       }
     }
     stage_layer<kWsThreads>(net, s, l, KI, KO, sm.Us, sm.Vs, sm.bs, sm.ss);
     __syncthreads();
     if (role == 0) {
-      if (first)
-        input_jets<NJ, RGM>(net, x, t, y);
-      else
+      if (first) {
+        if constexpr (JET)
+          input_jets<NJ, RGM>(net, x[0], t[0], y);
+        else
+          input_vals<NC, RGM>(net, x, t, y);
+      } else {
         ckpt_load<NJ, RGM>(ckbase + (l - 2) * kSlot, lane, y);
+      }
       const int RGI = first ? 1 : RGM;
 #pragma unroll
       for (int g = 0; g < RGM; ++g) {
@@ -591,7 +743,7 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
       else
         m2_bwd_loop<NJ, RGM, RGM, NG>(sm, xz, Gs, li, lane, y);
     } else if (role == 2) {
-      s0_bwd_loop<NJ, NG>(xa, xz, xg, Gs, lane, sm.bbar + trip * Wmax_p, amax);
+      s0_bwd_loop<NJ, NG>(xa, xz, xg, Gs, lane, sm.bbar + trip * Wm, 4 * Wm, amax);
     } else {
 #pragma unroll
       for (int c = 0; c < NJ; ++c)
@@ -601,21 +753,34 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
         s1_bwd_loop<NJ, RGM, 1, NG>(sm, xg, Gs, li, lane, y);
       else
         s1_bwd_loop<NJ, RGM, RGM, NG>(sm, xg, Gs, li, lane, y);
-      // dL/ds^l = sum_c wbar_c * y_c^l and ybar^l = s * wbar, one rank group at a time
+      // dL/ds^l = sum_c wbar_c * y_c^l (over the jets of a point; per column
+      // for value tiles) and ybar^l = s * wbar, one rank group at a time
       const int RGI = first ? 1 : RGM;
 #pragma unroll
       for (int g = 0; g < RGM; ++g) {
         if (g < RGI) {
           f4 yl[NJ];
-          if (first)
-            input_jets_g0<NJ>(net, x, t, yl);
-          else
+          if (first) {
+            if constexpr (JET)
+              input_jets_g0<NJ>(net, x[0], t[0], yl);
+            else
+              input_vals_g0<NC>(net, x, t, yl);
+          } else {
             ckpt_load_g<NJ, RGM>(ckbase + (l - 2) * kSlot, lane, g, yl);
-          f4 acc = zero4();
+          }
+          if constexpr (JET) {
+            f4 acc = zero4();
 #pragma unroll
-          for (int c = 0; c < NJ; ++c) acc += y[c][g] * yl[c];
-          const float tot = wave_sum4(acc, lane);
-          if ((lane & 15) == 0) sm.sbar[trip * RP + 4 * g + comp] = tot;
+            for (int c = 0; c < NJ; ++c) acc += y[c][g] * yl[c];
+            const float tot = wave_sum4(acc, lane);
+            if ((lane & 15) == 0) sm.sbar[trip * RP + 4 * g + comp] = tot;
+          } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              const float tot = wave_sum4(y[c][g] * yl[c], lane);
+              if ((lane & 15) == 0) sm.sbar[c * 4 * RP + trip * RP + 4 * g + comp] = tot;
+            }
+          }
           if (!first) {
             const f4 s4 = *reinterpret_cast<const f4*>(sm.ss + 4 * g);
 #pragma unroll
@@ -627,24 +792,40 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
       if (!first) ckpt_store<NJ, RGM>(ckbase + (l - 1) * kSlot, lane, y);
     }
     __syncthreads();
-    const int W = net.M[l], rl = net.r[l], Wm = Wmax_p;
-    for (int i = tid; i < W; i += kWsThreads)
-      rec[4 + net.r_total + net.offB[l] + i] =
-          ((sm.bbar[i] + sm.bbar[Wm + i]) + sm.bbar[2 * Wm + i]) + sm.bbar[3 * Wm + i];
-    for (int i = tid; i < rl; i += kWsThreads)
-      rec[4 + net.offS[l] + i] =
-          ((sm.sbar[i] + sm.sbar[RP + i]) + sm.sbar[2 * RP + i]) + sm.sbar[3 * RP + i];
+    const int W = net.M[l], rl = net.r[l];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      if (!tile_ok[c]) continue;
+      float* rec = tiles[c].rec;
+      const float* bb = sm.bbar + c * 4 * Wm;
+      const float* sb = sm.sbar + c * 4 * RP;
+      for (int i = tid; i < W; i += kWsThreads)
+        rec[4 + net.r_total + net.offB[l] + i] =
+            ((bb[i] + bb[Wm + i]) + bb[2 * Wm + i]) + bb[3 * Wm + i];
+      for (int i = tid; i < rl; i += kWsThreads)
+        rec[4 + net.offS[l] + i] = ((sb[i] + sb[RP + i]) + sb[2 * RP + i]) + sb[3 * RP + i];
+    }
   }
-  // flag the tile for the accurate relaunch if any lane met |a| > kFastRange
+  // flag the tiles for the accurate relaunch if any lane met |a| > kFastRange
   const bool bad = __any(!(amax <= kFastRange));
   __syncthreads();
-  if (lane == 0) sm.lw[16 + wave] = bad ? 1.f : 0.f;
+  if (lane == 0) sm.lw[16 * kMaxCols + wave] = bad ? 1.f : 0.f;
   __syncthreads();
   if (tid == 0) {
     float any = 0.f;
-    for (int w = 0; w < kWsWaves; ++w) any += sm.lw[16 + w];
-    *tile.flag = any > 0.f ? 1 : 0;
+    for (int w = 0; w < kWsWaves; ++w) any += sm.lw[16 * kMaxCols + w];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (tile_ok[c]) *tiles[c].flag = any > 0.f ? 1 : 0;
   }
+}
+
+// Value-only tiles of the plain gradient kernel take kMaxCols points per lane
+// (kMaxCols tiles per workgroup): every factor entry read from LDS then feeds
+// kMaxCols MFMAs, and the IC/BC workgroups are half as many.
+__host__ __device__ inline int ws_value_wgs(int G) { return (G + kMaxCols - 1) / kMaxCols; }
+__host__ __device__ inline int ws_grid_inst(const KGrid& g) {
+  return g.G_r + ws_value_wgs(g.G_0) + ws_value_wgs(g.G_b);
 }
 
 template <int RP>
@@ -653,26 +834,43 @@ __global__ __launch_bounds__(kWsThreads) void lrnr_grad_ws_kernel(KNet net, KIns
   extern __shared__ float4 smem_raw[];
   const SmemWS sm = ws_smem(reinterpret_cast<float*>(smem_raw), grid.Wmax_p, RP);
 
-  const int inst_id = blockIdx.x / grid.G_inst;
-  int wg = blockIdx.x - inst_id * grid.G_inst;
+  const int g0 = ws_value_wgs(grid.G_0);
+  const int per_inst = grid.G_r + g0 + ws_value_wgs(grid.G_b);
+  const int inst_id = blockIdx.x / per_inst;
+  int wg = blockIdx.x - inst_id * per_inst;
   int kind = 0;
-  if (wg >= grid.G_r + grid.G_0) {
+  if (wg >= grid.G_r + g0) {
     kind = 2;
-    wg -= grid.G_r + grid.G_0;
+    wg -= grid.G_r + g0;
   } else if (wg >= grid.G_r) {
     kind = 1;
     wg -= grid.G_r;
   }
   const float* s = inst.s + inst_id * grid.s_stride;
   const float* mu = inst.mu ? inst.mu + 3 * inst_id : nullptr;
-  KTile tile;
-  tile.rec = grid.partials + (int64_t)blockIdx.x * grid.P;
-  tile.ck = grid.ckpt + (int64_t)blockIdx.x * kWaves * grid.ckpt_per_wave;
-  tile.flag = grid.flags + blockIdx.x;
-  if (kind == 0)
-    ws_run<RP, 4, false>(net, inst, grid.ckpt_per_wave, grid.Wmax_p, tile, kind, wg, s, mu, sm);
-  else
-    ws_run<RP, 1, false>(net, inst, grid.ckpt_per_wave, grid.Wmax_p, tile, kind, wg, s, mu, sm);
+  // records and flags are per tile of the full grid (G_inst per instance)
+  const int64_t first = (int64_t)inst_id * grid.G_inst +
+                        (kind == 0 ? 0 : kind == 1 ? grid.G_r : grid.G_r + grid.G_0);
+  float* ck = grid.ckpt + (int64_t)blockIdx.x * kWaves * grid.ckpt_per_wave;
+  if (kind == 0) {
+    KTile tile;
+    tile.rec = grid.partials + (first + wg) * grid.P;
+    tile.ck = ck;
+    tile.flag = grid.flags + first + wg;
+    ws_run<RP, 4, false>(net, inst, grid.ckpt_per_wave, grid.Wmax_p, &tile, 0, wg, grid.G_r, s,
+                         mu, sm);
+  } else {
+    KTile tiles[kMaxCols];
+#pragma unroll
+    for (int c = 0; c < kMaxCols; ++c) {
+      const int64_t u = first + (int64_t)wg * kMaxCols + c;
+      tiles[c].rec = grid.partials + u * grid.P;
+      tiles[c].ck = ck;
+      tiles[c].flag = grid.flags + u;
+    }
+    ws_run<RP, kMaxCols, false>(net, inst, grid.ckpt_per_wave, grid.Wmax_p, tiles, kind, wg,
+                                kind == 1 ? grid.G_0 : grid.G_b, s, mu, sm);
+  }
 }
 
 // Rank tiles above this run the single-role kernel for the reverse modes:
@@ -744,11 +942,11 @@ __global__ __launch_bounds__(kWsThreads) void lrnr_grad_ws_table_kernel(KTableGr
     kt.ck = ck;
     kt.flag = tg.flags + tile;
     if (r.kind == 0)
-      ws_run<RP, 4, VJP>(T->net, T->inst, tg.ckpt_per_wave, tg.Wmax_p, kt, 0, r.wg, T->inst.s,
-                         T->inst.mu, sm);
+      ws_run<RP, 4, VJP>(T->net, T->inst, tg.ckpt_per_wave, tg.Wmax_p, &kt, 0, r.wg, r.wg + 1,
+                         T->inst.s, T->inst.mu, sm);
     else if constexpr (!VJP)
-      ws_run<RP, 1, false>(T->net, T->inst, tg.ckpt_per_wave, tg.Wmax_p, kt, r.kind, r.wg,
-                           T->inst.s, T->inst.mu, sm);
+      ws_run<RP, 1, false>(T->net, T->inst, tg.ckpt_per_wave, tg.Wmax_p, &kt, r.kind, r.wg,
+                           r.wg + 1, T->inst.s, T->inst.mu, sm);
     __syncthreads();
   }
 }
@@ -894,7 +1092,7 @@ hipError_t launch_grad_ws(const KNet& net, const KInst& inst, const KGrid& grid,
     if (e != hipSuccess) return e;
     return launch_one<RP, MODE_GRAD, SC_ACC>(net, inst, grid, stream);
   } else {
-    const dim3 blocks((unsigned)(grid.B * grid.G_inst)), threads(kWsThreads);
+    const dim3 blocks((unsigned)(grid.B * ws_grid_inst(grid))), threads(kWsThreads);
     const size_t lds = ws_lds_floats(RP, grid.Wmax_p) * sizeof(float);
     hipError_t e = set_lds(lrnr_grad_ws_kernel<RP>, lds);
     if (e != hipSuccess) return e;

@@ -127,7 +127,8 @@ def test_l1_form_and_locality_term():
 
 
 @pytest.mark.parametrize("n_r,n_0,n_b", [(1, 1, 1), (63, 0, 0), (65, 77, 33), (300, 1, 129),
-                                         (0, 50, 0), (0, 0, 40), (257, 256, 128)])
+                                         (0, 50, 0), (0, 0, 40), (257, 256, 128),
+                                         (130, 600, 300), (0, 1025, 385)])
 def test_ragged_and_empty_point_sets(n_r, n_0, n_b):
     w = custom(21, (2, 64, 64, 64, 1), 8, n_r, n_0, n_b)
     check_loss_grad(w, tag=f"ragged {n_r},{n_0},{n_b}")
