@@ -437,7 +437,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": r["achieved_tflops"] / FP32_MFMA_PEAK_TFLOPS,
             "traffic": measured_traffic(),
-            "kernel": "lrnr_grad_ws_kernel<20> (+ relaunch of flagged tiles)",
+            "kernel": "lrnr_grad_ws_kernel<20, 2> (+ relaunch of flagged tiles)",
             "kernel_ms_avg": r["kernel_ms_avg"],
             "flops_per_launch": r["flops_per_launch"],
         },

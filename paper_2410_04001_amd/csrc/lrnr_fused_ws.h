@@ -820,22 +820,25 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
   }
 }
 
-// Value-only tiles of the plain gradient kernel take kMaxCols points per lane
-// (kMaxCols tiles per workgroup): every factor entry read from LDS then feeds
-// kMaxCols MFMAs, and the IC/BC workgroups are half as many.
-__host__ __device__ inline int ws_value_wgs(int G) { return (G + kMaxCols - 1) / kMaxCols; }
-__host__ __device__ inline int ws_grid_inst(const KGrid& g) {
-  return g.G_r + ws_value_wgs(g.G_0) + ws_value_wgs(g.G_b);
+// Value-only tiles of the plain gradient kernel take NCV points per lane (NCV
+// tiles per workgroup).  With two, every factor entry read from LDS feeds two
+// MFMAs and the IC/BC workgroups are half as many, but each takes longer: it
+// pays when the value tiles outnumber the CUs (they would otherwise run in
+// more than one round after the interior ones), and one column is faster
+// when they fit in a single round.
+__host__ __device__ inline int ws_value_wgs(int G, int ncv) { return (G + ncv - 1) / ncv; }
+__host__ __device__ inline int ws_grid_inst(const KGrid& g, int ncv) {
+  return g.G_r + ws_value_wgs(g.G_0, ncv) + ws_value_wgs(g.G_b, ncv);
 }
 
-template <int RP>
+template <int RP, int NCV>
 __global__ __launch_bounds__(kWsThreads) void lrnr_grad_ws_kernel(KNet net, KInst inst,
                                                                   KGrid grid) {
   extern __shared__ float4 smem_raw[];
   const SmemWS sm = ws_smem(reinterpret_cast<float*>(smem_raw), grid.Wmax_p, RP);
 
-  const int g0 = ws_value_wgs(grid.G_0);
-  const int per_inst = grid.G_r + g0 + ws_value_wgs(grid.G_b);
+  const int g0 = ws_value_wgs(grid.G_0, NCV);
+  const int per_inst = grid.G_r + g0 + ws_value_wgs(grid.G_b, NCV);
   const int inst_id = blockIdx.x / per_inst;
   int wg = blockIdx.x - inst_id * per_inst;
   int kind = 0;
@@ -860,16 +863,16 @@ __global__ __launch_bounds__(kWsThreads) void lrnr_grad_ws_kernel(KNet net, KIns
     ws_run<RP, 4, false>(net, inst, grid.ckpt_per_wave, grid.Wmax_p, &tile, 0, wg, grid.G_r, s,
                          mu, sm);
   } else {
-    KTile tiles[kMaxCols];
+    KTile tiles[NCV];
 #pragma unroll
-    for (int c = 0; c < kMaxCols; ++c) {
-      const int64_t u = first + (int64_t)wg * kMaxCols + c;
+    for (int c = 0; c < NCV; ++c) {
+      const int64_t u = first + (int64_t)wg * NCV + c;
       tiles[c].rec = grid.partials + u * grid.P;
       tiles[c].ck = ck;
       tiles[c].flag = grid.flags + u;
     }
-    ws_run<RP, kMaxCols, false>(net, inst, grid.ckpt_per_wave, grid.Wmax_p, tiles, kind, wg,
-                                kind == 1 ? grid.G_0 : grid.G_b, s, mu, sm);
+    ws_run<RP, NCV, false>(net, inst, grid.ckpt_per_wave, grid.Wmax_p, tiles, kind, wg,
+                           kind == 1 ? grid.G_0 : grid.G_b, s, mu, sm);
   }
 }
 
@@ -1004,6 +1007,22 @@ static hipError_t set_lds(K kernel, size_t lds) {
   return e;
 }
 
+// Compute units of the current device (cached per device).
+static int device_cus() {
+  static std::mutex mu;
+  static std::map<int, int> cus;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cus.find(dev);
+  if (it != cus.end()) return it->second;
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+    n = 256;
+  cus[dev] = n;
+  return n;
+}
+
 template <typename K>
 static int resident_grid(K kernel, int threads, size_t lds) {
   if (set_lds(kernel, lds) != hipSuccess) return -1;
@@ -1092,11 +1111,22 @@ hipError_t launch_grad_ws(const KNet& net, const KInst& inst, const KGrid& grid,
     if (e != hipSuccess) return e;
     return launch_one<RP, MODE_GRAD, SC_ACC>(net, inst, grid, stream);
   } else {
-    const dim3 blocks((unsigned)(grid.B * ws_grid_inst(grid))), threads(kWsThreads);
+    const int64_t value_tiles = (int64_t)grid.B * (grid.G_0 + grid.G_b);
+    const bool two = value_tiles > device_cus();
+    const dim3 blocks((unsigned)(grid.B * ws_grid_inst(grid, two ? 2 : 1))), threads(kWsThreads);
     const size_t lds = ws_lds_floats(RP, grid.Wmax_p) * sizeof(float);
-    hipError_t e = set_lds(lrnr_grad_ws_kernel<RP>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((lrnr_grad_ws_kernel<RP>), blocks, threads, lds, stream, net, inst, grid);
+    hipError_t e;
+    if (two) {
+      e = set_lds(lrnr_grad_ws_kernel<RP, 2>, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((lrnr_grad_ws_kernel<RP, 2>), blocks, threads, lds, stream, net, inst,
+                         grid);
+    } else {
+      e = set_lds(lrnr_grad_ws_kernel<RP, 1>, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((lrnr_grad_ws_kernel<RP, 1>), blocks, threads, lds, stream, net, inst,
+                         grid);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     // workgroups that met |a| > kFastRange are recomputed with ocml's sin/cos

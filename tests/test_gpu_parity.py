@@ -134,6 +134,13 @@ def test_ragged_and_empty_point_sets(n_r, n_0, n_b):
     check_loss_grad(w, tag=f"ragged {n_r},{n_0},{n_b}")
 
 
+def test_ragged_value_tiles_beyond_the_cus():
+    """151 IC and 121 BC tiles (272 > 256 CUs): the IC/BC workgroups take two
+    tiles each, with a trailing workgroup that has one."""
+    w = custom(23, (2, 64, 64, 64, 1), 8, 130, 151 * 256 - 179, 121 * 128 - 95)
+    check_loss_grad(w, tag="value tiles beyond the CUs")
+
+
 def test_all_sets_empty_gives_zero():
     a = api()
     w = custom(22, (2, 32, 32, 1), 8, 0, 0, 0)
