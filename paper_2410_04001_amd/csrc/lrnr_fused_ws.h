@@ -881,6 +881,22 @@ __global__ __launch_bounds__(kWsThreads) void lrnr_grad_ws_kernel(KNet net, KIns
 // rank 20 a few long-lived values are spilled outside the MFMA loops).
 constexpr int kWsMaxRP = 20;
 
+// Which kernel runs the reverse modes.  The four-role kernel hides latency
+// with four waves per SIMD but pays a workgroup barrier per neuron step; when
+// a layer's factor block is small the single-role kernel (one wave owns its
+// points through the whole layer, no per-step barrier) is faster.  Measured
+// on the MI355X (loss + gradient, 4 hidden layers, 65536 points): rank tile
+// 4 by 28-31 % at every width up to 256; rank tiles 8 and 16 while
+// Wmax_p * RP <= 512; the four-role kernel above that (by 5-27 % at
+// Wmax_p * RP >= 1024).
+template <int RP>
+inline bool four_role(int Wmax_p) {
+  if constexpr (RP > kWsMaxRP)
+    return false;
+  else
+    return RP > 4 && Wmax_p * RP > 512;
+}
+
 // ---------------------------------------------------------------------------
 // Task-table launches: a persistent grid strides over the tiles of all tasks.
 // ---------------------------------------------------------------------------
@@ -1040,17 +1056,18 @@ static int resident_grid(K kernel, int threads, size_t lds) {
 template <int RP>
 int table_grid_rp(int mode, int Wmax_p) {
   if (reverse_mode(mode)) {
-    if constexpr (RP > kWsMaxRP) {
-      const size_t lds = fused_lds_bytes(RP, Wmax_p);
-      return mode == MODE_VJP
-                 ? resident_grid(lrnr_table_kernel<RP, MODE_VJP, SC_TRACK>, kThreads, lds)
-                 : resident_grid(lrnr_table_kernel<RP, MODE_GRAD, SC_TRACK>, kThreads, lds);
-    } else {
-      const size_t lds = ws_lds_floats(RP, Wmax_p) * sizeof(float);
-      return mode == MODE_VJP
-                 ? resident_grid(lrnr_grad_ws_table_kernel<RP, true>, kWsThreads, lds)
-                 : resident_grid(lrnr_grad_ws_table_kernel<RP, false>, kWsThreads, lds);
+    if constexpr (RP <= kWsMaxRP) {
+      if (four_role<RP>(Wmax_p)) {
+        const size_t lds = ws_lds_floats(RP, Wmax_p) * sizeof(float);
+        return mode == MODE_VJP
+                   ? resident_grid(lrnr_grad_ws_table_kernel<RP, true>, kWsThreads, lds)
+                   : resident_grid(lrnr_grad_ws_table_kernel<RP, false>, kWsThreads, lds);
+      }
     }
+    const size_t lds = fused_lds_bytes(RP, Wmax_p);
+    return mode == MODE_VJP
+               ? resident_grid(lrnr_table_kernel<RP, MODE_VJP, SC_TRACK>, kThreads, lds)
+               : resident_grid(lrnr_table_kernel<RP, MODE_GRAD, SC_TRACK>, kThreads, lds);
   }
   const size_t lds = fused_lds_bytes(RP, Wmax_p);
   switch (mode) {
@@ -1074,21 +1091,22 @@ static hipError_t launch_table_one(const KTableGrid& tg, int grid, hipStream_t s
 template <int RP, bool VJP>
 static hipError_t launch_table_rev(const KTableGrid& tg, int grid, hipStream_t stream) {
   constexpr int MODE = VJP ? MODE_VJP : MODE_GRAD;
-  if constexpr (RP > kWsMaxRP) {
-    hipError_t e = launch_table_one<RP, MODE, SC_TRACK>(tg, grid, stream);
-    if (e != hipSuccess) return e;
-    return launch_table_one<RP, MODE, SC_ACC>(tg, grid, stream);
-  } else {
-    const size_t lds = ws_lds_floats(RP, tg.Wmax_p) * sizeof(float);
-    hipError_t e = set_lds(lrnr_grad_ws_table_kernel<RP, VJP>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((lrnr_grad_ws_table_kernel<RP, VJP>), dim3(grid), dim3(kWsThreads), lds,
-                       stream, tg);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // tiles that met |a| > kFastRange are recomputed with ocml's sin/cos
-    return launch_table_one<RP, MODE, SC_ACC>(tg, grid, stream);
+  if constexpr (RP <= kWsMaxRP) {
+    if (four_role<RP>(tg.Wmax_p)) {
+      const size_t lds = ws_lds_floats(RP, tg.Wmax_p) * sizeof(float);
+      hipError_t e = set_lds(lrnr_grad_ws_table_kernel<RP, VJP>, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((lrnr_grad_ws_table_kernel<RP, VJP>), dim3(grid), dim3(kWsThreads), lds,
+                         stream, tg);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      // tiles that met |a| > kFastRange are recomputed with ocml's sin/cos
+      return launch_table_one<RP, MODE, SC_ACC>(tg, grid, stream);
+    }
   }
+  hipError_t e = launch_table_one<RP, MODE, SC_TRACK>(tg, grid, stream);
+  if (e != hipSuccess) return e;
+  return launch_table_one<RP, MODE, SC_ACC>(tg, grid, stream);
 }
 
 // grid: persistent workgroups; the checkpoint slab holds grid * kWaves slabs.
@@ -1106,11 +1124,14 @@ hipError_t launch_table_rp(int mode, const KTableGrid& tg, int grid, hipStream_t
 template <int RP>
 hipError_t launch_grad_ws(const KNet& net, const KInst& inst, const KGrid& grid,
                           hipStream_t stream) {
-  if constexpr (RP > kWsMaxRP) {
+  bool ws = false;
+  if constexpr (RP <= kWsMaxRP) ws = four_role<RP>(grid.Wmax_p);
+  if (!ws) {
     hipError_t e = launch_one<RP, MODE_GRAD, SC_TRACK>(net, inst, grid, stream);
     if (e != hipSuccess) return e;
     return launch_one<RP, MODE_GRAD, SC_ACC>(net, inst, grid, stream);
-  } else {
+  }
+  if constexpr (RP <= kWsMaxRP) {
     const int64_t value_tiles = (int64_t)grid.B * (grid.G_0 + grid.G_b);
     const bool two = value_tiles > device_cus();
     const dim3 blocks((unsigned)(grid.B * ws_grid_inst(grid, two ? 2 : 1))), threads(kWsThreads);
@@ -1132,6 +1153,7 @@ hipError_t launch_grad_ws(const KNet& net, const KInst& inst, const KGrid& grid,
     // workgroups that met |a| > kFastRange are recomputed with ocml's sin/cos
     return launch_one<RP, MODE_GRAD, SC_ACC>(net, inst, grid, stream);
   }
+  return hipSuccess;
 }
 
 template <int RP>

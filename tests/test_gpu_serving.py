@@ -2,7 +2,8 @@
 
 Checked: a request's tuned s, last loss and grid values are bitwise identical
 alone and in a mix with other requests arriving while it runs, with graph
-replay or direct launches, and with several steps per launch; they equal a
+replay or direct launches, and with several steps per launch, for FastLRNR
+models and for wider LRNR models (the two gradient kernels); they equal a
 plain loop of the task entry point and Adam; the grid values match the FP64
 oracle's FastLRNR forward at the tuned s; admission by arena footprint
 bounds the requests in flight.
@@ -166,3 +167,46 @@ def test_serving_admission_by_memory(models):
     alone = run_alone(models, SPECS[2])
     for x, y in zip(outputs(reqs[2]), alone):
         assert np.array_equal(x, y)
+
+
+@pytest.fixture(scope="module")
+def wide_models():
+    """Two LRNRs of widest layer 128 at rank tile 8: their gradient runs the
+    four-role kernel (the FastLRNR models above run the single-role one)."""
+    from paper_2410_04001_amd import api
+    out = []
+    for seed, M in ((61, [2, 128, 128, 128, 1]), (62, [2, 120, 100, 1])):
+        rng = np.random.Generator(np.random.PCG64(seed))
+        net = wl.make_net(rng, M, wl.ranks(M, 8))
+        out.append((api.DeviceNet.from_net(net), torch.tensor(net.s_flat(), device="cuda")))
+    return out
+
+
+def test_serving_alone_equals_mix_bitwise_wide_models(wide_models):
+    from paper_2410_04001_amd import serving
+    specs = [(0, 0, 3000, 21), (1, 1, 900, 22), (2, 0, 12000, 23), (3, 1, 700, 24)]
+    alone = {}
+    for sp in specs:
+        srv = serving.Server(wide_models, K=K)
+        (r,) = requests(srv, [sp])
+        srv.submit(r)
+        srv.run_until_done()
+        srv.close()
+        alone[sp[0]] = outputs(r)
+    for kw in ({}, {"use_graph": False, "max_inflight": 3}):
+        srv = serving.Server(wide_models, K=K, **kw)
+        reqs = requests(srv, specs)
+        srv.submit(reqs[0])
+        srv.submit(reqs[1])
+        for _ in range(5):
+            srv.poll()
+        for r in reqs[2:]:
+            srv.submit(r)
+        done = srv.run_until_done()
+        srv.close()
+        assert len(done) == len(specs)
+        for r in reqs:
+            for x, y in zip(outputs(r), alone[r.id]):
+                assert np.all(np.isfinite(x))
+                assert np.array_equal(x, y), (kw, r.id)
+    log(f"  wide models: every request bitwise equal alone and in the mixes")

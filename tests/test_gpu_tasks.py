@@ -71,12 +71,23 @@ class Inst:
         return [x.detach().cpu().numpy().copy() for x in (self.gs, self.gb, self.loss)]
 
 
-def nets():
-    n0 = wl.small_lrnr(0, 16).net                                   # (2,64,64,64,64,1), r 8
+def nets(kind="narrow"):
+    """Two nets per table.  narrow: widest layer 64 at rank tile 8 (the
+    reverse modes run the single-role kernel); wide: widest layer 128 at rank
+    tile 8 (the four-role kernel)."""
     rng = np.random.Generator(np.random.PCG64(21))
-    M = [2, 48, 40, 1]
+    if kind == "narrow":
+        n0 = wl.small_lrnr(0, 16).net                               # (2,64,64,64,64,1), r 8
+        M = [2, 48, 40, 1]
+    else:
+        M0 = [2, 128, 128, 128, 1]
+        n0 = wl.make_net(rng, M0, wl.ranks(M0, 8))
+        M = [2, 120, 100, 1]
     n1 = wl.make_net(rng, M, wl.ranks(M, 8))                        # other widths, depth
     return [n0, n1]
+
+
+KINDS = pytest.mark.parametrize("kind", ["narrow", "wide"])
 
 
 def run(mode, dnets, insts, cfg=None, out_attr=None):
@@ -92,14 +103,15 @@ def run(mode, dnets, insts, cfg=None, out_attr=None):
     torch.cuda.synchronize()
 
 
-def test_tasks_grad_loss_vs_oracle_and_single_path():
+@KINDS
+def test_tasks_grad_loss_vs_oracle_and_single_path(kind):
     a = api()
-    hn = nets()
+    hn = nets(kind)
     dn = [a.DeviceNet.from_net(n) for n in hn]
     shapes = [(0, 4096, 512, 512), (1, 1000, 77, 33), (0, 300, 0, 129), (1, 257, 256, 128)]
     insts = [Inst(sh[0], hn[sh[0]], 100 + i, *sh[1:]) for i, sh in enumerate(shapes)]
     cfg = a.LossCfg()
-    log(f"[case] task table GRAD, {len(insts)} tasks on two nets, shapes {shapes}")
+    log(f"[case] task table GRAD ({kind} nets), {len(insts)} tasks, shapes {shapes}")
     run(a.MODE_GRAD, dn, insts, cfg)
     for i, it in enumerate(insts):
         gs, gb, loss = it.outputs()
@@ -125,10 +137,11 @@ def test_tasks_grad_loss_vs_oracle_and_single_path():
         assert_close(it.loss.cpu().numpy(), l4, TOL, f"task {i} loss (LOSS mode)")
 
 
-def test_tasks_alone_equals_mix_bitwise():
+@KINDS
+def test_tasks_alone_equals_mix_bitwise(kind):
     """Each task's outputs do not depend on the other tasks of the launch."""
     a = api()
-    hn = nets()
+    hn = nets(kind)
     dn = [a.DeviceNet.from_net(n) for n in hn]
     mk = lambda: [Inst(0, hn[0], 200, 3000, 300, 300), Inst(1, hn[1], 201, 700, 90, 50),
                   Inst(0, hn[0], 202, 64, 8, 8, 0.9), Inst(1, hn[1], 203, 5000, 600, 600, 1.1)]
@@ -161,13 +174,14 @@ def test_tasks_alone_equals_mix_bitwise():
         log(f"  {name}: alone == mix bitwise over {len(mixes)} orderings of {len(pool)} tasks")
 
 
-def test_tasks_jets_value_vjp_vs_oracle():
+@KINDS
+def test_tasks_jets_value_vjp_vs_oracle(kind):
     a = api()
-    hn = nets()
+    hn = nets(kind)
     dn = [a.DeviceNet.from_net(n) for n in hn]
     insts = [Inst(0, hn[0], 300, 1500, 0, 0), Inst(1, hn[1], 301, 777, 0, 0),
              Inst(0, hn[0], 302, 1, 0, 0)]
-    log("[case] task table JETS / VALUE / VJP, 3 tasks on two nets")
+    log(f"[case] task table JETS / VALUE / VJP ({kind} nets), 3 tasks")
     run(a.MODE_JETS, dn, insts, out_attr="jets")
     run(a.MODE_VALUE, dn, insts, out_attr="val")
     run(a.MODE_VJP, dn, insts, out_attr="jets")
@@ -186,11 +200,12 @@ def test_tasks_jets_value_vjp_vs_oracle():
         assert_close(j, sj, 1e-6, f"task {i} jets vs lrnr_forward_jets")
 
 
-def test_tasks_empty_and_many():
+@KINDS
+def test_tasks_empty_and_many(kind):
     """Tasks with no points give zero loss and gradient; 150 tasks exercise
     the task search past one wave of candidates."""
     a = api()
-    hn = nets()
+    hn = nets(kind)
     dn = [a.DeviceNet.from_net(n) for n in hn]
     insts = []
     for i in range(150):
