@@ -800,9 +800,20 @@ __device__ __forceinline__ void run_kind(const KNet& net, const KInst& inst,
   }
 }
 
+// Waves per SIMD the compiler budgets registers for.  Rank tiles up to 8
+// fit two waves (256 registers) in every mode, which hides the latency of
+// the one-wave-per-point-group chain: measured 20-27 % faster for the
+// gradient at rank tile 8 than at the default budget (one wave, ~310
+// registers).  Rank tile 16 at two waves spills heavily (2x slower).
+template <int RP>
+constexpr int fused_waves_per_simd() {
+  return RP <= 8 ? 2 : 1;
+}
+
 template <int RP, int MODE, int SC>
-__global__ __launch_bounds__(kThreads) void lrnr_fused_kernel(KNet net, KInst inst,
-                                                              KGrid grid) {
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP>()))) void lrnr_fused_kernel(
+    KNet net, KInst inst, KGrid grid) {
   if constexpr (SC == SC_ACC) {
     if (grid.flags[blockIdx.x] == 0) return;  // only workgroups flagged by SC_TRACK
   }

@@ -882,19 +882,19 @@ __global__ __launch_bounds__(kWsThreads) void lrnr_grad_ws_kernel(KNet net, KIns
 constexpr int kWsMaxRP = 20;
 
 // Which kernel runs the reverse modes.  The four-role kernel hides latency
-// with four waves per SIMD but pays a workgroup barrier per neuron step; when
-// a layer's factor block is small the single-role kernel (one wave owns its
-// points through the whole layer, no per-step barrier) is faster.  Measured
-// on the MI355X (loss + gradient, 4 hidden layers, 65536 points): rank tile
-// 4 by 28-31 % at every width up to 256; rank tiles 8 and 16 while
-// Wmax_p * RP <= 512; the four-role kernel above that (by 5-27 % at
-// Wmax_p * RP >= 1024).
+// with four waves per SIMD but pays a workgroup barrier per neuron step; the
+// single-role kernel (one wave owns its points through the whole layer, no
+// per-step barrier) runs two waves per SIMD up to rank tile 8 and one above.
+// Measured on the MI355X (loss + gradient, 4 hidden layers, 65536 points,
+// widths 32-256): the single-role kernel is faster at rank tiles 4 and 8 at
+// every width (by 22-31 % at widths 128-256), and at rank tile 16 only while
+// Wmax_p * RP <= 512; the four-role kernel is faster above that (by 5-27 %).
 template <int RP>
 inline bool four_role(int Wmax_p) {
   if constexpr (RP > kWsMaxRP)
     return false;
   else
-    return RP > 4 && Wmax_p * RP > 512;
+    return RP > 8 && Wmax_p * RP > 512;
 }
 
 // ---------------------------------------------------------------------------
@@ -983,7 +983,9 @@ __device__ __forceinline__ Smem fused_smem(float* base, int Wm, int RP) {
 }
 
 template <int RP, int MODE, int SC>
-__global__ __launch_bounds__(kThreads) void lrnr_table_kernel(KTableGrid tg) {
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP>()))) void lrnr_table_kernel(
+    KTableGrid tg) {
   extern __shared__ float4 smem_raw[];
   const Smem sm = fused_smem(reinterpret_cast<float*>(smem_raw), tg.Wmax_p, RP);
   const KTableHdr* hdr = reinterpret_cast<const KTableHdr*>(tg.table);

@@ -127,26 +127,26 @@ def test_l1_form_and_locality_term():
 
 
 # width 64 at rank tile 8 runs the single-role kernel for the gradient, width
-# 128 the four-role kernel
-WIDTHS = pytest.mark.parametrize("width", [64, 128])
+# 128 at rank tile 16 the four-role kernel
+NETS = pytest.mark.parametrize("width,rank", [(64, 8), (128, 16)])
 
 
-@WIDTHS
+@NETS
 @pytest.mark.parametrize("n_r,n_0,n_b", [(1, 1, 1), (63, 0, 0), (65, 77, 33), (300, 1, 129),
                                          (0, 50, 0), (0, 0, 40), (257, 256, 128),
                                          (130, 600, 300), (0, 1025, 385)])
-def test_ragged_and_empty_point_sets(n_r, n_0, n_b, width):
-    w = custom(21, (2, width, width, width, 1), 8, n_r, n_0, n_b)
-    check_loss_grad(w, tag=f"ragged {n_r},{n_0},{n_b} width {width}")
+def test_ragged_and_empty_point_sets(n_r, n_0, n_b, width, rank):
+    w = custom(21, (2, width, width, width, 1), rank, n_r, n_0, n_b)
+    check_loss_grad(w, tag=f"ragged {n_r},{n_0},{n_b} width {width} rank {rank}")
 
 
-@WIDTHS
-def test_ragged_value_tiles_beyond_the_cus(width):
+@NETS
+def test_ragged_value_tiles_beyond_the_cus(width, rank):
     """151 IC and 121 BC tiles (272 > 256 CUs); in the four-role kernel the
     IC/BC workgroups take two tiles each, with a trailing workgroup that has
     one."""
-    w = custom(23, (2, width, width, width, 1), 8, 130, 151 * 256 - 179, 121 * 128 - 95)
-    check_loss_grad(w, tag=f"value tiles beyond the CUs, width {width}")
+    w = custom(23, (2, width, width, width, 1), rank, 130, 151 * 256 - 179, 121 * 128 - 95)
+    check_loss_grad(w, tag=f"value tiles beyond the CUs, width {width} rank {rank}")
 
 
 def test_all_sets_empty_gives_zero():
@@ -175,13 +175,13 @@ def test_net_shapes(M, rank):
     check_loss_grad(w, tag=f"shape {M}")
 
 
-@pytest.mark.parametrize("width", [32, 128])
-def test_large_preactivations_take_the_accurate_path(width):
+@NETS
+def test_large_preactivations_take_the_accurate_path(width, rank):
     """Four neurons of layer 1 get zero U-rows and bias 2^25, so their
     pre-activation is exactly 2^25 at every point (and the oracle exact).  The
     fast sin/cos reduction is not valid there (its quadrant index passes
     2^24); parity holds only if the accurate path is taken."""
-    w = custom(51, (2, width, width, width, 1), 8, 600, 70, 70)
+    w = custom(51, (2, width, width, width, 1), rank, 600, 70, 70)
     w.net.U[0][:4, :] = 0.0
     w.net.b[0][:4] = np.float32(2.0 ** 25)
     check_jets(w, tag="large |a|")
@@ -238,10 +238,10 @@ def test_big_net_full_size():
     assert_close(loss.cpu().numpy(), acc_l, 1e-5, "full loss vs sum of blocks")
 
 
-@pytest.mark.parametrize("width", [64, 128])
-def test_determinism_bitwise(width):
+@NETS
+def test_determinism_bitwise(width, rank):
     a = api()
-    w = wl.small_lrnr(0) if width == 64 else custom(24, (2, 128, 128, 128, 1), 8, 4096, 512, 512)
+    w = custom(24, (2, width, width, width, width, 1), rank, 4096, 512, 512)
     net, s, pts, mu = to_dev(w)
     outs = [a.grad_s(net, s, mu, pts, a.LossCfg()) for _ in range(3)]
     torch.cuda.synchronize()
@@ -250,10 +250,10 @@ def test_determinism_bitwise(width):
             assert torch.equal(x, y)
 
 
-@pytest.mark.parametrize("width", [64, 128])
-def test_batched_equals_single_bitwise(width):
+@NETS
+def test_batched_equals_single_bitwise(width, rank):
     a = api()
-    w = wl.small_lrnr(0, 1000) if width == 64 else custom(25, (2, 128, 128, 128, 1), 8, 1000, 125, 125)
+    w = custom(25, (2, width, width, width, width, 1), rank, 1000, 125, 125)
     net, s, pts, _ = to_dev(w)
     rng = np.random.default_rng(4)
     B = 5

@@ -171,13 +171,13 @@ def test_serving_admission_by_memory(models):
 
 @pytest.fixture(scope="module")
 def wide_models():
-    """Two LRNRs of widest layer 128 at rank tile 8: their gradient runs the
+    """Two LRNRs of widest layer 128 at rank tile 16: their gradient runs the
     four-role kernel (the FastLRNR models above run the single-role one)."""
     from paper_2410_04001_amd import api
     out = []
     for seed, M in ((61, [2, 128, 128, 128, 1]), (62, [2, 120, 100, 1])):
         rng = np.random.Generator(np.random.PCG64(seed))
-        net = wl.make_net(rng, M, wl.ranks(M, 8))
+        net = wl.make_net(rng, M, wl.ranks(M, 16))
         out.append((api.DeviceNet.from_net(net), torch.tensor(net.s_flat(), device="cuda")))
     return out
 

@@ -74,16 +74,16 @@ class Inst:
 def nets(kind="narrow"):
     """Two nets per table.  narrow: widest layer 64 at rank tile 8 (the
     reverse modes run the single-role kernel); wide: widest layer 128 at rank
-    tile 8 (the four-role kernel)."""
+    tile 16 (the four-role kernel)."""
     rng = np.random.Generator(np.random.PCG64(21))
     if kind == "narrow":
         n0 = wl.small_lrnr(0, 16).net                               # (2,64,64,64,64,1), r 8
-        M = [2, 48, 40, 1]
+        M, rank = [2, 48, 40, 1], 8
     else:
         M0 = [2, 128, 128, 128, 1]
-        n0 = wl.make_net(rng, M0, wl.ranks(M0, 8))
-        M = [2, 120, 100, 1]
-    n1 = wl.make_net(rng, M, wl.ranks(M, 8))                        # other widths, depth
+        n0 = wl.make_net(rng, M0, wl.ranks(M0, 16))
+        M, rank = [2, 120, 100, 1], 13
+    n1 = wl.make_net(rng, M, wl.ranks(M, rank))                     # other widths, depth
     return [n0, n1]
 
 
