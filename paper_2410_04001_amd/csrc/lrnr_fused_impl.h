@@ -804,15 +804,19 @@ __device__ __forceinline__ void run_kind(const KNet& net, const KInst& inst,
 // fit two waves (256 registers) in every mode, which hides the latency of
 // the one-wave-per-point-group chain: measured 20-27 % faster for the
 // gradient at rank tile 8 than at the default budget (one wave, ~310
-// registers).  Rank tile 16 at two waves spills heavily (2x slower).
-template <int RP>
+// registers); the forward-only modes (jets, value, loss) there take three
+// waves (168 registers, a few values spilled outside the loops; the
+// differentiation-form step, whose forward is a loss-only launch, ~2 %
+// faster).  Rank tile 16 at two waves spills heavily (2x slower).
+template <int RP, int MODE>
 constexpr int fused_waves_per_simd() {
-  return RP <= 8 ? 2 : 1;
+  if (RP > 8) return 1;
+  return MODE == MODE_GRAD || MODE == MODE_VJP ? 2 : 3;
 }
 
 template <int RP, int MODE, int SC>
 __global__ __launch_bounds__(kThreads)
-__attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP>()))) void lrnr_fused_kernel(
+__attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP, MODE>()))) void lrnr_fused_kernel(
     KNet net, KInst inst, KGrid grid) {
   if constexpr (SC == SC_ACC) {
     if (grid.flags[blockIdx.x] == 0) return;  // only workgroups flagged by SC_TRACK

@@ -984,7 +984,7 @@ __device__ __forceinline__ Smem fused_smem(float* base, int Wm, int RP) {
 
 template <int RP, int MODE, int SC>
 __global__ __launch_bounds__(kThreads)
-__attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP>()))) void lrnr_table_kernel(
+__attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP, MODE>()))) void lrnr_table_kernel(
     KTableGrid tg) {
   extern __shared__ float4 smem_raw[];
   const Smem sm = fused_smem(reinterpret_cast<float*>(smem_raw), tg.Wmax_p, RP);
