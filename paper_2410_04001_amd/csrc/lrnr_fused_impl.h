@@ -451,7 +451,8 @@ struct Smem {
 };
 
 // Stage layer l's U^l [Wp][KI], V^{l+1} [Wp][KO], b^l [Wp] and s^l [KI] into
-// LDS with zero padding (NT threads cooperate).
+// LDS with zero padding (threads 0..NT-1 cooperate; ss == nullptr leaves
+// s^l out).
 template <int NT>
 __device__ void stage_layer(const KNet& net, const float* __restrict__ s, int l, int KI,
                             int KO, float* __restrict__ Us, float* __restrict__ Vs,
@@ -484,7 +485,8 @@ __device__ void stage_layer(const KNet& net, const float* __restrict__ s, int l,
     }
   }
   for (int i = threadIdx.x; i < Wp; i += NT) bs[i] = i < W ? b[i] : 0.f;
-  for (int i = threadIdx.x; i < KI; i += NT) ss[i] = i < rl ? s[net.offS[l] + i] : 0.f;
+  if (ss)
+    for (int i = threadIdx.x; i < KI; i += NT) ss[i] = i < rl ? s[net.offS[l] + i] : 0.f;
 }
 
 // Jets of y^1 = V^1T (x, t): value V^1T (x,t), d/dx row 0 of V^1, d/dt row 1,

@@ -688,12 +688,13 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
   }
 
   // ---- reverse sweep -----------------------------------------------------------
-  for (int l = L - 1; l >= 1; --l) {
-    const bool first = l == 1, last = l == L - 1;
-    const int KI = first ? 4 : RP, KO = last ? 4 : RP;
-    const int Gs = (((net.M[l] + 3) & ~3) / 4 + NG - 1) / NG;
-    __syncthreads();
-    if (l == L - 1 && tid < 4 * NC) {
+  // Layer L-1 is staged here; every later layer is staged by waves 0-11 while
+  // S1 finishes the ds term of the layer before (s^l, which that term still
+  // reads, after the following barrier).
+  __syncthreads();
+  {
+    const int l = L - 1;
+    if (tid < 4 * NC) {
       const int c = tid >> 2, e = tid & 3;
       const float* lw = sm.lw + 16 * c;
       const float v = ((lw[e] + lw[4 + e]) + lw[8 + e]) + lw[12 + e];
@@ -711,7 +712,11 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
         }
       }
     }
-    stage_layer<kWsThreads>(net, s, l, KI, KO, sm.Us, sm.Vs, sm.bs, sm.ss);
+    stage_layer<kWsThreads>(net, s, l, l == 1 ? 4 : RP, 4, sm.Us, sm.Vs, sm.bs, sm.ss);
+  }
+  for (int l = L - 1; l >= 1; --l) {
+    const bool first = l == 1, last = l == L - 1;
+    const int Gs = (((net.M[l] + 3) & ~3) / 4 + NG - 1) / NG;
     __syncthreads();
     if (role == 0) {
       if (first) {
@@ -791,7 +796,17 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
       // ybar^l goes to slot l-1 (y^{l+1} there is no longer needed)
       if (!first) ckpt_store<NJ, RGM>(ckbase + (l - 1) * kSlot, lane, y);
     }
+    // waves 0-11: U^{l-1}, V^l and b^{l-1} of the next layer (this layer's
+    // loops are over, and S1's ds term reads only s^l and the checkpoints)
+    if (role != 3 && !first)
+      stage_layer<kWsThreads - 256>(net, s, l - 1, l - 1 == 1 ? 4 : RP, RP, sm.Us, sm.Vs,
+                                    sm.bs, nullptr);
     __syncthreads();
+    if (!first) {
+      const int KIn = l - 1 == 1 ? 4 : RP, rn = net.r[l - 1];
+      for (int i = tid; i < KIn; i += kWsThreads)
+        sm.ss[i] = i < rn ? s[net.offS[l - 1] + i] : 0.f;
+    }
     const int W = net.M[l], rl = net.r[l];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
