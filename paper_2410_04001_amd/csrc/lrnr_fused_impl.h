@@ -451,12 +451,13 @@ struct Smem {
 };
 
 // Stage layer l's U^l [Wp][KI], V^{l+1} [Wp][KO], b^l [Wp] and s^l [KI] into
-// LDS with zero padding (threads 0..NT-1 cooperate; ss == nullptr leaves
-// s^l out).
+// LDS with zero padding.  NT threads cooperate, numbered by tix in [0, NT)
+// (threadIdx.x by default); ss == nullptr leaves s^l out.
 template <int NT>
 __device__ void stage_layer(const KNet& net, const float* __restrict__ s, int l, int KI,
                             int KO, float* __restrict__ Us, float* __restrict__ Vs,
-                            float* __restrict__ bs, float* __restrict__ ss) {
+                            float* __restrict__ bs, float* __restrict__ ss, int tix = -1) {
+  const int tx = tix < 0 ? (int)threadIdx.x : tix;
   // rows padded to a multiple of 16 (value-only tiles step over 16 neurons)
   const int W = net.M[l], Wp = (W + 15) & ~15, rl = net.r[l], ro = net.r[l + 1];
   const float* __restrict__ U = net.U + net.offU[l];
@@ -466,27 +467,27 @@ __device__ void stage_layer(const KNet& net, const float* __restrict__ s, int l,
   // float4 when 16-byte aligned, which takes a quarter of the round trips
   if (rl == KI && (reinterpret_cast<uintptr_t>(U) & 15) == 0) {
     const f4* __restrict__ src = reinterpret_cast<const f4*>(U);
-    for (int i = threadIdx.x; i < W * KI / 4; i += NT) reinterpret_cast<f4*>(Us)[i] = src[i];
-    for (int i = W * KI + threadIdx.x; i < Wp * KI; i += NT) Us[i] = 0.f;
+    for (int i = tx; i < W * KI / 4; i += NT) reinterpret_cast<f4*>(Us)[i] = src[i];
+    for (int i = W * KI + tx; i < Wp * KI; i += NT) Us[i] = 0.f;
   } else {
-    for (int i = threadIdx.x; i < Wp * KI; i += NT) {
+    for (int i = tx; i < Wp * KI; i += NT) {
       const int w = i / KI, k = i - w * KI;
       Us[i] = (w < W && k < rl) ? U[w * rl + k] : 0.f;
     }
   }
   if (ro == KO && (reinterpret_cast<uintptr_t>(V) & 15) == 0) {
     const f4* __restrict__ src = reinterpret_cast<const f4*>(V);
-    for (int i = threadIdx.x; i < W * KO / 4; i += NT) reinterpret_cast<f4*>(Vs)[i] = src[i];
-    for (int i = W * KO + threadIdx.x; i < Wp * KO; i += NT) Vs[i] = 0.f;
+    for (int i = tx; i < W * KO / 4; i += NT) reinterpret_cast<f4*>(Vs)[i] = src[i];
+    for (int i = W * KO + tx; i < Wp * KO; i += NT) Vs[i] = 0.f;
   } else {
-    for (int i = threadIdx.x; i < Wp * KO; i += NT) {
+    for (int i = tx; i < Wp * KO; i += NT) {
       const int w = i / KO, k = i - w * KO;
       Vs[i] = (w < W && k < ro) ? V[w * ro + k] : 0.f;
     }
   }
-  for (int i = threadIdx.x; i < Wp; i += NT) bs[i] = i < W ? b[i] : 0.f;
+  for (int i = tx; i < Wp; i += NT) bs[i] = i < W ? b[i] : 0.f;
   if (ss)
-    for (int i = threadIdx.x; i < KI; i += NT) ss[i] = i < rl ? s[net.offS[l] + i] : 0.f;
+    for (int i = tx; i < KI; i += NT) ss[i] = i < rl ? s[net.offS[l] + i] : 0.f;
 }
 
 // Jets of y^1 = V^1T (x, t): value V^1T (x,t), d/dx row 0 of V^1, d/dt row 1,

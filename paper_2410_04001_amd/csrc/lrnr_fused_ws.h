@@ -497,6 +497,40 @@ __device__ __forceinline__ void input_vals_g0(const KNet& net, const float (&x)[
     y[c] = f4{v00 * x[c] + v10 * t[c], v01 * x[c] + v11 * t[c], 0.f, 0.f};
 }
 
+// A tile's reduced jets (NJ x RGM f4 per lane) handed from one wave to another
+// at a layer boundary through the tile's exchange slots, five slots of 4 f4
+// per lane in the order xz[0], xz[1], xg[0], xg[1], xa[1].  At the first step
+// of the next layer only xa[0] (M1, forward and reverse) and xz[0] (M2,
+// reverse, after its own read) are written, so the reader takes them at that
+// step and nothing else touches them before the step's barrier.
+__device__ __forceinline__ float* yx_slot(float* xa, float* xz, float* xg, int i) {
+  const int q = i >> 2;
+  float* base = q == 0 ? xz : q == 1 ? xz + kXFloats : q == 2 ? xg : q == 3 ? xg + kXFloats
+                                                                         : xa + kXFloats;
+  return base + (i & 3) * 64 * 4;
+}
+
+template <int NJ, int RGM>
+__device__ __forceinline__ void yx_put(float* xa, float* xz, float* xg, int lane,
+                                       const f4 (&y)[NJ][RGM]) {
+  static_assert(NJ * RGM <= 20, "five exchange slots of 4 f4 per lane");
+#pragma unroll
+  for (int c = 0; c < NJ; ++c)
+#pragma unroll
+    for (int g = 0; g < RGM; ++g)
+      *reinterpret_cast<f4*>(yx_slot(xa, xz, xg, c * RGM + g) + lane * 4) = y[c][g];
+}
+
+template <int NJ, int RGM>
+__device__ __forceinline__ void yx_get(float* xa, float* xz, float* xg, int lane,
+                                       f4 (&y)[NJ][RGM]) {
+#pragma unroll
+  for (int c = 0; c < NJ; ++c)
+#pragma unroll
+    for (int g = 0; g < RGM; ++g)
+      y[c][g] = *reinterpret_cast<const f4*>(yx_slot(xa, xz, xg, c * RGM + g) + lane * 4);
+}
+
 // ---------------------------------------------------------------------------
 // Workgroup driver (MODE_GRAD / MODE_VJP, fast sin/cos with range tracking).
 //
@@ -559,12 +593,14 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
   f4 y[NJ][RGM];
 
   // ---- forward sweep ----------------------------------------------------------
+  // Layer 1 is staged here; every later layer by waves 0-3 and 8-15 while M2
+  // stores the layer's output, which it also hands to M1 through the tile's
+  // exchange slots (the global checkpoint is for the reverse sweep).
+  __syncthreads();
+  stage_layer<kWsThreads>(net, s, 1, 4, L - 1 == 1 ? 4 : RP, sm.Us, sm.Vs, sm.bs, sm.ss);
   for (int l = 1; l <= L - 1; ++l) {
     const bool first = l == 1, last = l == L - 1;
-    const int KI = first ? 4 : RP, KO = last ? 4 : RP;
     const int Gs = (((net.M[l] + 3) & ~3) / 4 + NG - 1) / NG;
-    __syncthreads();
-    stage_layer<kWsThreads>(net, s, l, KI, KO, sm.Us, sm.Vs, sm.bs, sm.ss);
     __syncthreads();
     if (role == 0) {
       if (first) {
@@ -573,7 +609,7 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
         else
           input_vals<NC, RGM>(net, x, t, y);
       } else {
-        ckpt_load<NJ, RGM>(ckbase + (l - 2) * kSlot, lane, y);
+        yx_get<NJ, RGM>(xa, xz, xg, lane, y);
       }
       const int RGI = first ? 1 : RGM;
 #pragma unroll
@@ -599,8 +635,16 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
         m2_fwd_loop<NJ, RGM, 1, NG>(sm, xz, Gs, li, lane, y);
       else
         m2_fwd_loop<NJ, RGM, RGM, NG>(sm, xz, Gs, li, lane, y);
-      if (!last) ckpt_store<NJ, RGM>(ckbase + (l - 1) * kSlot, lane, y);
+      if (!last) {
+        ckpt_store<NJ, RGM>(ckbase + (l - 1) * kSlot, lane, y);
+        yx_put<NJ, RGM>(xa, xz, xg, lane, y);
+      }
     }
+    // the loops of this layer are over: the next layer's factors go to LDS
+    // (threads of waves 0-3 and 8-15 numbered 0..767)
+    if (!last && role != 1)
+      stage_layer<kWsThreads - 256>(net, s, l + 1, RP, l + 1 == L - 1 ? 4 : RP, sm.Us, sm.Vs,
+                                    sm.bs, sm.ss, role == 0 ? tid : tid - 256);
   }
 
   // ---- output layer, residual and loss adjoints (M2) --------------------------
@@ -688,12 +732,12 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
   }
 
   // ---- reverse sweep -----------------------------------------------------------
-  // Layer L-1 is staged here; every later layer is staged by waves 0-11 while
-  // S1 finishes the ds term of the layer before (s^l, which that term still
-  // reads, after the following barrier).
+  // Layer L-1 is still staged from the forward sweep.  Every later layer is staged by waves 0-11 while S1 finishes
+  // the ds term of the layer before (s^l, which that term still reads, after
+  // the following barrier); S1 hands ybar^l to the next layer's M2 through
+  // the tile's exchange slots.
   __syncthreads();
   {
-    const int l = L - 1;
     if (tid < 4 * NC) {
       const int c = tid >> 2, e = tid & 3;
       const float* lw = sm.lw + 16 * c;
@@ -712,7 +756,6 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
         }
       }
     }
-    stage_layer<kWsThreads>(net, s, l, l == 1 ? 4 : RP, 4, sm.Us, sm.Vs, sm.bs, sm.ss);
   }
   for (int l = L - 1; l >= 1; --l) {
     const bool first = l == 1, last = l == L - 1;
@@ -741,8 +784,8 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
       else
         m1_loop<NJ, RGM, RGM, NG>(sm, xa, Gs, Gs + 2, li, lane, y);
     } else if (role == 1) {
-      // ybar^{l+1} was left in slot l by S1 at the end of layer l+1
-      if (!last) ckpt_load<NJ, RGM>(ckbase + l * kSlot, lane, y);
+      // ybar^{l+1} from S1 at the end of layer l+1, through the exchange slots
+      if (!last) yx_get<NJ, RGM>(xa, xz, xg, lane, y);
       if (last)
         m2_bwd_loop<NJ, RGM, 1, NG>(sm, xz, Gs, li, lane, y);
       else
@@ -793,8 +836,8 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
           }
         }
       }
-      // ybar^l goes to slot l-1 (y^{l+1} there is no longer needed)
-      if (!first) ckpt_store<NJ, RGM>(ckbase + (l - 1) * kSlot, lane, y);
+      // ybar^l to the next layer's M2
+      if (!first) yx_put<NJ, RGM>(xa, xz, xg, lane, y);
     }
     // waves 0-11: U^{l-1}, V^l and b^{l-1} of the next layer (this layer's
     // loops are over, and S1's ds term reads only s^l and the checkpoints)
