@@ -9,6 +9,24 @@
 
 namespace lrnr {
 
+// Sum of n values base[0], base[stride], ... in FP64, added strictly in index
+// order; the loads are issued eight at a time, so the order (and the result)
+// is that of the plain loop while the memory latency is paid n/8 times.
+template <typename T>
+__device__ __forceinline__ double ordered_sum(const T* __restrict__ base, int64_t stride, int n) {
+  double acc = 0.0;
+  int i = 0;
+  for (; i + 8 <= n; i += 8) {
+    T v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = base[(int64_t)(i + j) * stride];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc += (double)v[j];
+  }
+  for (; i < n; ++i) acc += (double)base[(int64_t)i * stride];
+  return acc;
+}
+
 // Stage 1: red1[i][c][e] = sum of records [c*kRedChunk, (c+1)*kRedChunk) of
 // instance i, element e.
 __global__ void reduce_stage1(const float* __restrict__ partials, double* __restrict__ red1,
@@ -17,18 +35,13 @@ __global__ void reduce_stage1(const float* __restrict__ partials, double* __rest
   const int c = blockIdx.y, inst = blockIdx.z;
   if (e >= E) return;
   const int r0 = c * kRedChunk, r1 = min(G_inst, r0 + kRedChunk);
-  const float* base = partials + ((int64_t)inst * G_inst) * P + e;
-  double acc = 0.0;
-  for (int r = r0; r < r1; ++r) acc += (double)base[(int64_t)r * P];
-  red1[((int64_t)inst * nchunk + c) * P + e] = acc;
+  const float* base = partials + ((int64_t)inst * G_inst + r0) * P + e;
+  red1[((int64_t)inst * nchunk + c) * P + e] = ordered_sum(base, P, r1 - r0);
 }
 
 __device__ __forceinline__ double column_sum(const double* __restrict__ red1, int inst,
                                              int nchunk, int P, int e) {
-  const double* base = red1 + (int64_t)inst * nchunk * P + e;
-  double acc = 0.0;
-  for (int c = 0; c < nchunk; ++c) acc += base[(int64_t)c * P];
-  return acc;
+  return ordered_sum(red1 + (int64_t)inst * nchunk * P + e, P, nchunk);
 }
 
 __device__ __forceinline__ float sgn(float v) { return v > 0.f ? 1.f : (v < 0.f ? -1.f : 0.f); }
@@ -121,9 +134,7 @@ __global__ __launch_bounds__(kTableReduceThreads) void table_reduce_kernel(KTabl
       double acc = 0.0;
       for (int c = 0; c < nchunk; ++c) {
         const int r0 = c * kRedChunk, r1 = min(G, r0 + kRedChunk);
-        double cs = 0.0;
-        for (int r = r0; r < r1; ++r) cs += (double)rec[(int64_t)r * P + e];
-        acc += cs;
+        acc += ordered_sum(rec + (int64_t)r0 * P + e, P, r1 - r0);
       }
       if (e < 4) {
         sums[e] = acc;
