@@ -315,12 +315,17 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lrnr_grad_ws_N262144_w256_r20_tra
 
 
 def kernel_source_sha():
-    """SHA-256 over the sources of the working-size gradient kernel."""
+    """SHA-256 over the code of the working-size gradient kernel's sources:
+    lines with their // comments removed, blank lines dropped, so that an
+    edit of comments alone keeps the stored counter figures valid."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2410_04001_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2410_04001_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()
 
 

@@ -24,9 +24,11 @@
 // The role loops are separate code paths with equal barrier counts (the
 // hardware barrier counts waves, not program locations).
 //
-// Between layers the reduced jets travel through the tile's global
-// checkpoint slab: M2 writes y^{l+1} (forward), S1 writes ybar^l (reverse),
-// and M1 / M2 read them after the next barrier.
+// Between layers the reduced jets pass from wave to wave through the tile's
+// exchange slots (M2 -> M1: y^{l+1} forward; S1 -> M2: ybar^l reverse).  The
+// forward y^{l+1} also go to the tile's global checkpoint slab, from which
+// M1 (U-side recompute) and S1 (ds term) read them in the reverse sweep.
+// Layers are staged into LDS by the waves that are idle at the boundary.
 #pragma once
 
 #include <algorithm>
