@@ -50,7 +50,7 @@ struct SmemWS {
   float* Us;
   float* Vs;
   float* bs;
-  float* ss;
+  float* ss;    // [2][RP]: s^l of layer l in buffer l & 1
   float* xa;    // [4 tiles][2 slots][kXFloats]  a                     (M1 -> S)
   float* xz;    // [4 tiles][2 slots][kXFloats]  z (S -> M2) / zbar (M2 -> S0)
   float* xg;    // [4 tiles][2 slots][kXFloats]  abar                  (S0 -> S1)
@@ -60,7 +60,7 @@ struct SmemWS {
 };
 
 inline size_t ws_lds_floats(int RP, int Wmax_p) {
-  return (size_t)Wmax_p * RP * 2 + Wmax_p + RP + (size_t)3 * 4 * 2 * kXFloats +
+  return (size_t)Wmax_p * RP * 2 + Wmax_p + 2 * RP + (size_t)3 * 4 * 2 * kXFloats +
          (size_t)kMaxCols * 4 * (Wmax_p + RP) + 16 * (kMaxCols + 1);
 }
 
@@ -70,7 +70,7 @@ __device__ __forceinline__ SmemWS ws_smem(float* base, int Wm, int RP) {
   sm.Vs = sm.Us + Wm * RP;
   sm.bs = sm.Vs + Wm * RP;
   sm.ss = sm.bs + Wm;
-  sm.xa = sm.ss + RP;
+  sm.xa = sm.ss + 2 * RP;
   sm.xz = sm.xa + 4 * 2 * kXFloats;
   sm.xg = sm.xz + 4 * 2 * kXFloats;
   sm.bbar = sm.xg + 4 * 2 * kXFloats;
@@ -524,6 +524,14 @@ __device__ __forceinline__ void yx_put(float* xa, float* xz, float* xg, int lane
 }
 
 template <int NJ, int RGM>
+__device__ __forceinline__ void yx_get_g(float* xa, float* xz, float* xg, int lane, int g,
+                                         f4 (&y)[NJ]) {
+#pragma unroll
+  for (int c = 0; c < NJ; ++c)
+    y[c] = *reinterpret_cast<const f4*>(yx_slot(xa, xz, xg, c * RGM + g) + lane * 4);
+}
+
+template <int NJ, int RGM>
 __device__ __forceinline__ void yx_get(float* xa, float* xz, float* xg, int lane,
                                        f4 (&y)[NJ][RGM]) {
 #pragma unroll
@@ -599,7 +607,7 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
   // stores the layer's output, which it also hands to M1 through the tile's
   // exchange slots (the global checkpoint is for the reverse sweep).
   __syncthreads();
-  stage_layer<kWsThreads>(net, s, 1, 4, L - 1 == 1 ? 4 : RP, sm.Us, sm.Vs, sm.bs, sm.ss);
+  stage_layer<kWsThreads>(net, s, 1, 4, L - 1 == 1 ? 4 : RP, sm.Us, sm.Vs, sm.bs, sm.ss + RP);
   for (int l = 1; l <= L - 1; ++l) {
     const bool first = l == 1, last = l == L - 1;
     const int Gs = (((net.M[l] + 3) & ~3) / 4 + NG - 1) / NG;
@@ -617,7 +625,7 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
 #pragma unroll
       for (int g = 0; g < RGM; ++g) {
         if (g < RGI) {
-          const f4 s4 = *reinterpret_cast<const f4*>(sm.ss + 4 * g);
+          const f4 s4 = *reinterpret_cast<const f4*>(sm.ss + (l & 1) * RP + 4 * g);
 #pragma unroll
           for (int c = 0; c < NJ; ++c) y[c][g] *= s4;
         }
@@ -646,7 +654,8 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
     // (threads of waves 0-3 and 8-15 numbered 0..767)
     if (!last && role != 1)
       stage_layer<kWsThreads - 256>(net, s, l + 1, RP, l + 1 == L - 1 ? 4 : RP, sm.Us, sm.Vs,
-                                    sm.bs, sm.ss, role == 0 ? tid : tid - 256);
+                                    sm.bs, sm.ss + ((l + 1) & 1) * RP,
+                                    role == 0 ? tid : tid - 256);
   }
 
   // ---- output layer, residual and loss adjoints (M2) --------------------------
@@ -776,7 +785,7 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
 #pragma unroll
       for (int g = 0; g < RGM; ++g) {
         if (g < RGI) {
-          const f4 s4 = *reinterpret_cast<const f4*>(sm.ss + 4 * g);
+          const f4 s4 = *reinterpret_cast<const f4*>(sm.ss + (l & 1) * RP + 4 * g);
 #pragma unroll
           for (int c = 0; c < NJ; ++c) y[c][g] *= s4;
         }
@@ -786,8 +795,18 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
       else
         m1_loop<NJ, RGM, RGM, NG>(sm, xa, Gs, Gs + 2, li, lane, y);
     } else if (role == 1) {
-      // ybar^{l+1} from S1 at the end of layer l+1, through the exchange slots
-      if (!last) yx_get<NJ, RGM>(xa, xz, xg, lane, y);
+      // wbar^{l+1} from S1 at the end of layer l+1, through the exchange
+      // slots; ybar^{l+1} = s^{l+1} * wbar^{l+1} (s^{l+1} is in the other
+      // s buffer)
+      if (!last) {
+        yx_get<NJ, RGM>(xa, xz, xg, lane, y);
+#pragma unroll
+        for (int g = 0; g < RGM; ++g) {
+          const f4 s4 = *reinterpret_cast<const f4*>(sm.ss + ((l + 1) & 1) * RP + 4 * g);
+#pragma unroll
+          for (int c = 0; c < NJ; ++c) y[c][g] = s4 * y[c][g];
+        }
+      }
       if (last)
         m2_bwd_loop<NJ, RGM, 1, NG>(sm, xz, Gs, li, lane, y);
       else
@@ -803,54 +822,64 @@ __device__ void ws_run(const KNet& net, const KInst& inst, int64_t ckpt_per_wave
         s1_bwd_loop<NJ, RGM, 1, NG>(sm, xg, Gs, li, lane, y);
       else
         s1_bwd_loop<NJ, RGM, RGM, NG>(sm, xg, Gs, li, lane, y);
-      // dL/ds^l = sum_c wbar_c * y_c^l (over the jets of a point; per column
-      // for value tiles) and ybar^l = s * wbar, one rank group at a time
-      const int RGI = first ? 1 : RGM;
+      // dL/ds^l = sum_c wbar_c * y_c^l over the jets of a point (per column
+      // for value tiles), one rank group at a time.  Above the input layer
+      // wbar^l first goes to the next layer's M2 through the exchange slots,
+      // which frees its registers for y^l, read in one round trip; wbar is
+      // read back from LDS group by group.
+      if (first) {
+        f4 yl[NJ];
+        if constexpr (JET)
+          input_jets_g0<NJ>(net, x[0], t[0], yl);
+        else
+          input_vals_g0<NC>(net, x, t, yl);
+        if constexpr (JET) {
+          f4 acc = zero4();
 #pragma unroll
-      for (int g = 0; g < RGM; ++g) {
-        if (g < RGI) {
-          f4 yl[NJ];
-          if (first) {
-            if constexpr (JET)
-              input_jets_g0<NJ>(net, x[0], t[0], yl);
-            else
-              input_vals_g0<NC>(net, x, t, yl);
-          } else {
-            ckpt_load_g<NJ, RGM>(ckbase + (l - 2) * kSlot, lane, g, yl);
+          for (int c = 0; c < NJ; ++c) acc += y[c][0] * yl[c];
+          const float tot = wave_sum4(acc, lane);
+          if ((lane & 15) == 0) sm.sbar[trip * RP + comp] = tot;
+        } else {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            const float tot = wave_sum4(y[c][0] * yl[c], lane);
+            if ((lane & 15) == 0) sm.sbar[c * 4 * RP + trip * RP + comp] = tot;
           }
+        }
+      } else {
+        yx_put<NJ, RGM>(xa, xz, xg, lane, y);
+        ckpt_load<NJ, RGM>(ckbase + (l - 2) * kSlot, lane, y);
+#pragma unroll
+        for (int g = 0; g < RGM; ++g) {
+          f4 wg[NJ];
+          yx_get_g<NJ, RGM>(xa, xz, xg, lane, g, wg);
           if constexpr (JET) {
             f4 acc = zero4();
 #pragma unroll
-            for (int c = 0; c < NJ; ++c) acc += y[c][g] * yl[c];
+            for (int c = 0; c < NJ; ++c) acc += wg[c] * y[c][g];
             const float tot = wave_sum4(acc, lane);
             if ((lane & 15) == 0) sm.sbar[trip * RP + 4 * g + comp] = tot;
           } else {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-              const float tot = wave_sum4(y[c][g] * yl[c], lane);
+              const float tot = wave_sum4(wg[c] * y[c][g], lane);
               if ((lane & 15) == 0) sm.sbar[c * 4 * RP + trip * RP + 4 * g + comp] = tot;
             }
           }
-          if (!first) {
-            const f4 s4 = *reinterpret_cast<const f4*>(sm.ss + 4 * g);
-#pragma unroll
-            for (int c = 0; c < NJ; ++c) y[c][g] = s4 * y[c][g];
-          }
         }
       }
-      // ybar^l to the next layer's M2
-      if (!first) yx_put<NJ, RGM>(xa, xz, xg, lane, y);
     }
     // waves 0-11: U^{l-1}, V^l and b^{l-1} of the next layer (this layer's
-    // loops are over, and S1's ds term reads only s^l and the checkpoints)
+    // loops are over, and S1's ds term reads only the checkpoints and the
+    // exchange slots)
     if (role != 3 && !first)
       stage_layer<kWsThreads - 256>(net, s, l - 1, l - 1 == 1 ? 4 : RP, RP, sm.Us, sm.Vs,
                                     sm.bs, nullptr);
     __syncthreads();
     if (!first) {
       const int KIn = l - 1 == 1 ? 4 : RP, rn = net.r[l - 1];
-      for (int i = tid; i < KIn; i += kWsThreads)
-        sm.ss[i] = i < rn ? s[net.offS[l - 1] + i] : 0.f;
+      float* ssn = sm.ss + ((l - 1) & 1) * RP;
+      for (int i = tid; i < KIn; i += kWsThreads) ssn[i] = i < rn ? s[net.offS[l - 1] + i] : 0.f;
     }
     const int W = net.M[l], rl = net.r[l];
 #pragma unroll
