@@ -450,6 +450,19 @@ struct Smem {
   float* lw;     // [kWaves][4]
 };
 
+// dst[i] = src[i] for i < n (float4), two loads in flight per thread.
+template <int NT>
+__device__ __forceinline__ void copy_f4(f4* __restrict__ dst, const f4* __restrict__ src, int n,
+                                        int tx) {
+  int i = tx;
+  for (; i + NT < n; i += 2 * NT) {
+    const f4 a = src[i], b = src[i + NT];
+    dst[i] = a;
+    dst[i + NT] = b;
+  }
+  if (i < n) dst[i] = src[i];
+}
+
 // Stage layer l's U^l [Wp][KI], V^{l+1} [Wp][KO], b^l [Wp] and s^l [KI] into
 // LDS with zero padding.  NT threads cooperate, numbered by tix in [0, NT)
 // (threadIdx.x by default); ss == nullptr leaves s^l out.
@@ -466,8 +479,7 @@ __device__ void stage_layer(const KNet& net, const float* __restrict__ s, int l,
   // a factor whose rank fills the tile is one contiguous block: copied as
   // float4 when 16-byte aligned, which takes a quarter of the round trips
   if (rl == KI && (reinterpret_cast<uintptr_t>(U) & 15) == 0) {
-    const f4* __restrict__ src = reinterpret_cast<const f4*>(U);
-    for (int i = tx; i < W * KI / 4; i += NT) reinterpret_cast<f4*>(Us)[i] = src[i];
+    copy_f4<NT>(reinterpret_cast<f4*>(Us), reinterpret_cast<const f4*>(U), W * KI / 4, tx);
     for (int i = W * KI + tx; i < Wp * KI; i += NT) Us[i] = 0.f;
   } else {
     for (int i = tx; i < Wp * KI; i += NT) {
@@ -476,8 +488,7 @@ __device__ void stage_layer(const KNet& net, const float* __restrict__ s, int l,
     }
   }
   if (ro == KO && (reinterpret_cast<uintptr_t>(V) & 15) == 0) {
-    const f4* __restrict__ src = reinterpret_cast<const f4*>(V);
-    for (int i = tx; i < W * KO / 4; i += NT) reinterpret_cast<f4*>(Vs)[i] = src[i];
+    copy_f4<NT>(reinterpret_cast<f4*>(Vs), reinterpret_cast<const f4*>(V), W * KO / 4, tx);
     for (int i = W * KO + tx; i < Wp * KO; i += NT) Vs[i] = 0.f;
   } else {
     for (int i = tx; i < Wp * KO; i += NT) {
