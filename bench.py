@@ -135,6 +135,59 @@ def run_fast(args, torch, api, wl):
     }
 
 
+def run_fidelity(args, torch, api, wl):
+    """FastLRNR fidelity against the reduced width r_hat (the sweep of
+    Fig. 2 (bottom), on a synthetic net): on the small net (64 wide, rank 8)
+    with the 65536 training points of the FastLRNR comparison, the FastLRNR
+    loss and grad_s against the LRNR's at the same s, and u at 16384 held-out
+    points, for DEIM built from snapshots at s alone and at s plus 7
+    perturbed copies (each entry scaled by 1 + 0.1 N(0, 1)); with the build
+    time and the FastLRNR loss+grad time."""
+    import numpy as np
+    w = wl.fast_case(2)
+    net = api.DeviceNet.from_net(w.net)
+    s_host = w.net.s_flat()
+    s = torch.tensor(s_host, device="cuda")
+    pts = api.DevicePoints.from_points(w.pts)
+    mu = torch.tensor(w.mu[0], device="cuda")
+    cfg = api.LossCfg()
+    xs = torch.tensor(w.extra["xt_snap"], device="cuda")
+    rng = np.random.Generator(np.random.PCG64(9))
+    xt_held = torch.tensor(wl.uniform_points(rng, 16384), device="cuda")
+    pert = [s_host] + [(s_host * (1.0 + 0.1 * rng.standard_normal(s_host.shape))).astype(np.float32)
+                       for _ in range(7)]
+    snaps = {"s": s.reshape(1, -1), "s + 7 perturbed": torch.tensor(np.stack(pert), device="cuda")}
+    gs_l, _, loss_l = api.grad_s(net, s, mu, pts, cfg, with_b=False)
+    u_l = api.forward_value(net, s, xt_held)
+    ms_l = time_calls(torch, lambda: api.grad_s(net, s, mu, pts, cfg, with_b=False), 20, 3)
+    torch.cuda.synchronize()
+    gl = gs_l.double()
+    rows = []
+    for r_hat in (8, 12, 16, 24, 32, 48, 64):
+        for name, snap in snaps.items():
+            torch.cuda.synchronize()
+            t = time.time()
+            fast = api.FastLRNR(net, snap, xs, r_hat)
+            torch.cuda.synchronize()
+            build_ms = (time.time() - t) * 1e3
+            gs_f, loss_f = fast.grad_s(s, mu, pts, cfg)
+            u_f = api.forward_value(fast.net, s, xt_held)
+            ms_f = time_calls(torch, lambda: fast.grad_s(s, mu, pts, cfg), 20, 3)
+            gf = gs_f.double()
+            rows.append({
+                "r_hat": r_hat, "snapshots": name,
+                "grad_rel_err": float((gf - gl).norm() / gl.norm()),
+                "grad_cosine": float((gf @ gl) / (gf.norm() * gl.norm())),
+                "loss_rel_err": float(abs(loss_f[0].double() - loss_l[0].double()) / loss_l[0].double()),
+                "u_heldout_rel_err": float((u_f.double() - u_l.double()).norm() / u_l.double().norm()),
+                "build_ms": build_ms, "fastlrnr_grad_ms": ms_f, "lrnr_grad_ms": ms_l,
+            })
+            fast.close()
+    return {"workload": "small net 64 wide x 4 hidden, rank 8; N=65536 (+8192 IC, +8192 BC); "
+                        "2048 snapshot points; 16384 held-out points",
+            "rows": rows}
+
+
 def run_equal_accuracy(args, torch, api, wl, big):
     """FastLRNR against LRNR at equal residual accuracy.  From s_init, Adam
     (lr 1e-3) with the LRNR gradient and, separately, with the FastLRNR
@@ -392,6 +445,7 @@ def main():
     ap.add_argument("--no-equal-acc", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-fidelity", action="store_true")
     ap.add_argument("--serve-rates", type=lambda x: [float(v) for v in x.split(",")],
                     default=[50, 100, 200, 500, 1000, 2000])
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -449,6 +503,8 @@ def main():
     }
     if fast is not None:
         out["fastlrnr"] = fast
+    if not args.no_fidelity:
+        out["fidelity"] = run_fidelity(args, torch, api, wl)
     if not args.no_equal_acc:
         out["equal_accuracy"] = [run_equal_accuracy(args, torch, api, wl, big)
                                  for big in (False, True)]
