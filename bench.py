@@ -140,9 +140,9 @@ def run_fidelity(args, torch, api, wl):
     Fig. 2 (bottom), on a synthetic net): on the small net (64 wide, rank 8)
     with the 65536 training points of the FastLRNR comparison, the FastLRNR
     loss and grad_s against the LRNR's at the same s, and u at 16384 held-out
-    points, for DEIM built from snapshots at s alone and at s plus 7
-    perturbed copies (each entry scaled by 1 + 0.1 N(0, 1)); with the build
-    time and the FastLRNR loss+grad time."""
+    points, for DEIM and Q-DEIM index selection, each from snapshots at s
+    alone and at s plus 7 perturbed copies (each entry scaled by
+    1 + 0.1 N(0, 1)); with the build time and the FastLRNR loss+grad time."""
     import numpy as np
     w = wl.fast_case(2)
     net = api.DeviceNet.from_net(w.net)
@@ -164,25 +164,26 @@ def run_fidelity(args, torch, api, wl):
     gl = gs_l.double()
     rows = []
     for r_hat in (8, 12, 16, 24, 32, 48, 64):
-        for name, snap in snaps.items():
-            torch.cuda.synchronize()
-            t = time.time()
-            fast = api.FastLRNR(net, snap, xs, r_hat)
-            torch.cuda.synchronize()
-            build_ms = (time.time() - t) * 1e3
-            gs_f, loss_f = fast.grad_s(s, mu, pts, cfg)
-            u_f = api.forward_value(fast.net, s, xt_held)
-            ms_f = time_calls(torch, lambda: fast.grad_s(s, mu, pts, cfg), 20, 3)
-            gf = gs_f.double()
-            rows.append({
-                "r_hat": r_hat, "snapshots": name,
-                "grad_rel_err": float((gf - gl).norm() / gl.norm()),
-                "grad_cosine": float((gf @ gl) / (gf.norm() * gl.norm())),
-                "loss_rel_err": float(abs(loss_f[0].double() - loss_l[0].double()) / loss_l[0].double()),
-                "u_heldout_rel_err": float((u_f.double() - u_l.double()).norm() / u_l.double().norm()),
-                "build_ms": build_ms, "fastlrnr_grad_ms": ms_f, "lrnr_grad_ms": ms_l,
-            })
-            fast.close()
+        for sel in ("deim", "qdeim"):
+            for name, snap in snaps.items():
+                torch.cuda.synchronize()
+                t = time.time()
+                fast = api.FastLRNR(net, snap, xs, r_hat, selection=sel)
+                torch.cuda.synchronize()
+                build_ms = (time.time() - t) * 1e3
+                gs_f, loss_f = fast.grad_s(s, mu, pts, cfg)
+                u_f = api.forward_value(fast.net, s, xt_held)
+                ms_f = time_calls(torch, lambda: fast.grad_s(s, mu, pts, cfg), 20, 3)
+                gf = gs_f.double()
+                rows.append({
+                    "r_hat": r_hat, "selection": sel, "snapshots": name,
+                    "grad_rel_err": float((gf - gl).norm() / gl.norm()),
+                    "grad_cosine": float((gf @ gl) / (gf.norm() * gl.norm())),
+                    "loss_rel_err": float(abs(loss_f[0].double() - loss_l[0].double()) / loss_l[0].double()),
+                    "u_heldout_rel_err": float((u_f.double() - u_l.double()).norm() / u_l.double().norm()),
+                    "build_ms": build_ms, "fastlrnr_grad_ms": ms_f, "lrnr_grad_ms": ms_l,
+                })
+                fast.close()
     return {"workload": "small net 64 wide x 4 hidden, rank 8; N=65536 (+8192 IC, +8192 BC); "
                         "2048 snapshot points; 16384 held-out points",
             "rows": rows}

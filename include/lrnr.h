@@ -342,6 +342,23 @@ int32_t fastlrnr_build(const lrnr_net* net, const float* s_snap, int32_t n_s,
                        const float* xt_snap, int64_t n_snap, const int32_t* r_hat,
                        fastlrnr_handle** out, void* stream);
 
+/* Index selection of fastlrnr_build_sel. */
+#define LRNR_SEL_DEIM 0  /* greedy DEIM (as fastlrnr_build)                       */
+#define LRNR_SEL_QDEIM 1 /* Q-DEIM: first r_hat pivots of the column-pivoted QR of
+                            Xi^T (Drmac & Gugercin 2016; the alternative the
+                            fidelity study compares), ties to the smallest index */
+
+/*
+ * fastlrnr_build with a choice of index selection (LRNR_SEL_DEIM or
+ * LRNR_SEL_QDEIM); the snapshots, POD basis and the reduced operators of
+ * eq. 2.7 are the same for both.  Other selection values return
+ * LRNR_EINVAL; LRNR_ESINGULAR as fastlrnr_build, or when Q-DEIM finds no row
+ * with a nonzero remaining norm (Xi of deficient rank).
+ */
+int32_t fastlrnr_build_sel(const lrnr_net* net, const float* s_snap, int32_t n_s,
+                           const float* xt_snap, int64_t n_snap, const int32_t* r_hat,
+                           int32_t selection, fastlrnr_handle** out, void* stream);
+
 /* Reduced net of a handle as an lrnr_net (widths r_hat, device pointers owned
  * by the handle): usable with every lrnr_* entry point. */
 int32_t fastlrnr_get_net(const fastlrnr_handle* h, lrnr_net* out);

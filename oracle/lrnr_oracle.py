@@ -343,6 +343,27 @@ def deim_indices(Xi):
     return np.array(P, dtype=np.int64)
 
 
+def qdeim_indices(Xi):
+    """Q-DEIM (Drmac & Gugercin 2016): the first r indices of a column-pivoted
+    QR factorisation of Xi^T.  Written as modified Gram-Schmidt on the rows of
+    Xi: each step takes the row of largest remaining 2-norm (ties to the
+    smallest index) and removes its direction from every row."""
+    W = _f(Xi).copy()
+    M, r = W.shape
+    picked = np.zeros(M, dtype=bool)
+    P = []
+    for _ in range(r):
+        nrm = np.where(picked, 0.0, np.sum(W * W, axis=1))
+        p = int(np.argmax(nrm))
+        if not nrm[p] > 0.0:
+            raise np.linalg.LinAlgError("Q-DEIM: no row with a nonzero remaining norm")
+        q = W[p] / np.sqrt(nrm[p])
+        W -= np.outer(W @ q, q)
+        picked[p] = True
+        P.append(p)
+    return np.array(P, dtype=np.int64)
+
+
 def fast_operators(net, P_list, Xi_list):
     """Reduced operators of eq. 2.7 for every hidden layer l = 1..L-1:
     U_hat^l = P^T U^l, b_hat^l = P^T b^l,
@@ -357,11 +378,12 @@ def fast_operators(net, P_list, Xi_list):
     return Uh, bh, Vh
 
 
-def fastlrnr_build(net, s_snap_list, xt_snap, r_hat, P_override=None):
+def fastlrnr_build(net, s_snap_list, xt_snap, r_hat, P_override=None, selection="deim"):
     """Snapshots of the hidden states at the snapshot points, POD basis, DEIM
-    indices and reduced operators.  ``s_snap_list`` is a list of coefficient
-    vectors (each a per-layer list).  ``P_override`` replaces the DEIM picks
-    (used to compare against a selection made elsewhere)."""
+    (or, with selection="qdeim", Q-DEIM) indices and reduced operators.
+    ``s_snap_list`` is a list of coefficient vectors (each a per-layer list).
+    ``P_override`` replaces the picks (used to compare against a selection
+    made elsewhere)."""
     L = net.L
     if np.isscalar(r_hat):
         r_hat = [int(r_hat)] * (L - 1)
@@ -373,7 +395,10 @@ def fastlrnr_build(net, s_snap_list, xt_snap, r_hat, P_override=None):
     for l in range(L - 1):
         Z = np.concatenate(Zs[l], axis=1)
         Xi = pod_basis(Z, r_hat[l])
-        P = deim_indices(Xi) if P_override is None else np.asarray(P_override[l])
+        if P_override is not None:
+            P = np.asarray(P_override[l])
+        else:
+            P = qdeim_indices(Xi) if selection == "qdeim" else deim_indices(Xi)
         Xi_list.append(Xi)
         P_list.append(P)
     Uh, bh, Vh = fast_operators(net, P_list, Xi_list)

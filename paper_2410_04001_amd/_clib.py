@@ -46,6 +46,7 @@ class LrnrLossCfg(C.Structure):
     ]
 
 
+SEL_DEIM, SEL_QDEIM = 0, 1  # include/lrnr.h LRNR_SEL_*
 MODE_JETS, MODE_VALUE, MODE_LOSS, MODE_GRAD, MODE_VJP = 0, 1, 2, 3, 4
 
 
@@ -128,6 +129,7 @@ SIGNATURES = {
     "lrnr_srv_get_stats": (I32, [P, C.POINTER(LrnrSrvStats)]),
     "lrnr_srv_destroy": (I32, [P]),
     "fastlrnr_build": (I32, [NETP, P, I32, P, I64, C.POINTER(I32), C.POINTER(P), P]),
+    "fastlrnr_build_sel": (I32, [NETP, P, I32, P, I64, C.POINTER(I32), I32, C.POINTER(P), P]),
     "fastlrnr_get_net": (I32, [P, NETP]),
     "fastlrnr_get_indices": (I32, [P, C.POINTER(I32)]),
     "fastlrnr_grad_s": (I32, [P, P, P, PTSP, CFGP, P, P, P, SZ, P]),

@@ -323,7 +323,8 @@ class FastLRNR:
     """A FastLRNR built on the device by fastlrnr_build (eq. 2.7); its reduced
     net runs through the same entry points as the LRNR."""
 
-    def __init__(self, net, s_snap, xt_snap, r_hat):
+    def __init__(self, net, s_snap, xt_snap, r_hat, selection="deim"):
+        """selection: "deim" (greedy DEIM) or "qdeim" (pivoted-QR selection)."""
         L = net.L
         if np.isscalar(r_hat):
             r_hat = [int(r_hat)] * (L - 1)
@@ -331,9 +332,10 @@ class FastLRNR:
         rh = (C.c_int32 * (L - 1))(*self.r_hat)
         h = C.c_void_p()
         s_snap = s_snap.reshape(-1, net.r_total).contiguous()
-        cl.check(cl.lib().fastlrnr_build(net.c(), _p(s_snap), s_snap.shape[0], _p(xt_snap),
-                                         xt_snap.shape[0], rh, C.byref(h), _stream()),
-                 "fastlrnr_build")
+        sel = {"deim": cl.SEL_DEIM, "qdeim": cl.SEL_QDEIM}[selection]
+        cl.check(cl.lib().fastlrnr_build_sel(net.c(), _p(s_snap), s_snap.shape[0], _p(xt_snap),
+                                             xt_snap.shape[0], rh, sel, C.byref(h), _stream()),
+                 "fastlrnr_build_sel")
         self._h = h
         cnet = cl.LrnrNet()
         cl.check(cl.lib().fastlrnr_get_net(h, C.byref(cnet)), "fastlrnr_get_net")

@@ -182,6 +182,7 @@ struct SelArgs {
   float* bh;                  // [r_hat] out
   float* Vh;                  // [r_hat][ro] out
   int* status;                // set to 1 on breakdown
+  int qdeim;                  // index selection: 0 DEIM, 1 Q-DEIM
 };
 
 __global__ __launch_bounds__(kSelThreads) void select_kernel(SelArgs a) {
@@ -312,9 +313,49 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(SelArgs a) {
   }
   __syncthreads();
 
+  // ---- Q-DEIM: column-pivoted QR of Xi^T (Drmac & Gugercin 2016) ----------
+  // The rows of Xi are the columns of Xi^T.  Step j takes the row of largest
+  // remaining norm (ties to the smallest index) and removes its direction
+  // from every row (modified Gram-Schmidt); the picks are the first r_hat
+  // pivots of the pivoted QR.  E (no longer needed) holds the rows.
+  if (a.qdeim) {
+    double* W = a.E;      // [M][rh]
+    double* nrm = a.R;    // [M]
+    double* qv = a.A;     // [rh]
+    for (int e = tid; e < M * rh; e += nt) W[e] = a.Xi[e];
+    for (int i = tid; i < M; i += nt) a.rank[i] = 0;  // 1 once picked
+    __syncthreads();
+    for (int j = 0; j < rh; ++j) {
+      for (int i = tid; i < M; i += nt) {
+        double acc = 0.0;
+        for (int k = 0; k < rh; ++k) acc += W[(int64_t)i * rh + k] * W[(int64_t)i * rh + k];
+        nrm[i] = a.rank[i] ? 0.0 : acc;
+      }
+      __syncthreads();
+      const int pj = wg_argmax_abs(nrm, M, 1, sh);
+      if (nrm[pj] <= 0.0) {
+        if (tid == 0) *a.status = 1;
+        return;
+      }
+      const double inv = 1.0 / sqrt(nrm[pj]);
+      for (int k = tid; k < rh; k += nt) qv[k] = W[(int64_t)pj * rh + k] * inv;
+      if (tid == 0) {
+        a.P[j] = pj;
+        a.rank[pj] = 1;
+      }
+      __syncthreads();
+      for (int i = tid; i < M; i += nt) {
+        double d = 0.0;
+        for (int k = 0; k < rh; ++k) d += W[(int64_t)i * rh + k] * qv[k];
+        for (int k = 0; k < rh; ++k) W[(int64_t)i * rh + k] -= d * qv[k];
+      }
+      __syncthreads();
+    }
+  }
+
   // ---- DEIM greedy -------------------------------------------------------
   double* res = a.R;
-  for (int j = 0; j < rh; ++j) {
+  for (int j = 0; j < rh && !a.qdeim; ++j) {
     if (j == 0) {
       for (int i = tid; i < M; i += nt) res[i] = a.Xi[(int64_t)i * rh];
       __syncthreads();
@@ -385,12 +426,13 @@ hipError_t dalloc(T** p, size_t n) {
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-int32_t fastlrnr_build(const lrnr_net* net, const float* s_snap, int32_t n_s,
-                       const float* xt_snap, int64_t n_snap, const int32_t* r_hat,
-                       fastlrnr_handle** out, void* stream) {
+int32_t build(const lrnr_net* net, const float* s_snap, int32_t n_s, const float* xt_snap,
+              int64_t n_snap, const int32_t* r_hat, int32_t selection, fastlrnr_handle** out,
+              void* stream) {
   if (!net || !s_snap || !xt_snap || !r_hat || !out) return LRNR_EINVAL;
+  if (selection != LRNR_SEL_DEIM && selection != LRNR_SEL_QDEIM) return LRNR_EINVAL;
   *out = nullptr;
   const int L = net->L;
   if (L < 2 || L > LRNR_MAX_LAYERS || net->M[0] != 2 || net->M[L] != 1) return LRNR_EINVAL;
@@ -501,6 +543,7 @@ int32_t fastlrnr_build(const lrnr_net* net, const float* s_snap, int32_t n_s,
       sa.bh = h->b + boff;
       sa.Vh = h->V + voff;
       sa.status = status;
+      sa.qdeim = selection == LRNR_SEL_QDEIM;
       hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kSelThreads), 0, hs, sa);
       TRY(hipGetLastError());
       zoff += (size_t)ncols * M;
@@ -525,7 +568,8 @@ int32_t fastlrnr_build(const lrnr_net* net, const float* s_snap, int32_t n_s,
 done:
 #undef TRY
   if (e != hipSuccess) set_status_detail(hipGetErrorString(e));
-  if (rc == LRNR_ESINGULAR) set_status_detail("zero pivot in the DEIM or V_hat system");
+  if (rc == LRNR_ESINGULAR)
+    set_status_detail("zero pivot in the DEIM or V_hat system, or no row left for Q-DEIM");
   (void)hipFree(Z);
   (void)hipFree(E);
   (void)hipFree(Xi);
@@ -543,6 +587,22 @@ done:
   rn.b = h->b;
   *out = h;
   return LRNR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t fastlrnr_build(const lrnr_net* net, const float* s_snap, int32_t n_s,
+                       const float* xt_snap, int64_t n_snap, const int32_t* r_hat,
+                       fastlrnr_handle** out, void* stream) {
+  return build(net, s_snap, n_s, xt_snap, n_snap, r_hat, LRNR_SEL_DEIM, out, stream);
+}
+
+int32_t fastlrnr_build_sel(const lrnr_net* net, const float* s_snap, int32_t n_s,
+                           const float* xt_snap, int64_t n_snap, const int32_t* r_hat,
+                           int32_t selection, fastlrnr_handle** out, void* stream) {
+  return build(net, s_snap, n_s, xt_snap, n_snap, r_hat, selection, out, stream);
 }
 
 int32_t fastlrnr_get_net(const fastlrnr_handle* h, lrnr_net* out) {

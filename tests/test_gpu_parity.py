@@ -369,6 +369,46 @@ def test_fastlrnr_build_from_perturbed_snapshots_matches_oracle():
     fast.close()
 
 
+@pytest.mark.parametrize("n_sets", [1, 4])
+def test_fastlrnr_qdeim_matches_oracle(n_sets):
+    """Q-DEIM selection (fastlrnr_build_sel) at r_hat = 8, from snapshots at
+    s alone and at s plus 3 perturbed copies: the device picks the oracle's
+    indices on the resolved spectrum, and the FastLRNR loss and gradient
+    match the oracle's eq. 2.8 chain on the device's operators."""
+    a = api()
+    w = wl.fast_case(2, n=8192)
+    xs = w.extra["xt_snap"]
+    rng = np.random.Generator(np.random.PCG64(9))
+    s0 = w.net.s_flat()
+    snaps = [s0] + [(s0 * (1.0 + 0.1 * rng.standard_normal(s0.shape))).astype(np.float32)
+                    for _ in range(n_sets - 1)]
+    s_lists = [w.net.split_s(v) for v in snaps]
+    Z = [np.concatenate(zs, axis=0) for zs in
+         zip(*[orc.lrnr_hidden_values(w.net, sl, xs) for sl in s_lists])]
+    k = []
+    for z in Z:
+        sv = np.linalg.svd(z.T, compute_uv=False)
+        k.append(int(np.sum(sv >= 1e-8 * sv[0])))
+    log(f"[case] fastlrnr Q-DEIM r_hat=8, {n_sets} snapshot sets, resolved modes {k}")
+    net, s, pts, mu = to_dev(w)
+    fast = a.FastLRNR(net, torch.tensor(np.stack(snaps), device="cuda"),
+                      torch.tensor(xs, device="cuda"), 8, selection="qdeim")
+    P = fast.indices()
+    ref = orc.fastlrnr_build(w.net, s_lists, xs, 8, selection="qdeim")
+    for p, q, kl in zip(P, ref["P"], k):
+        n_eq = int(np.argmin(np.append(p == q, False)))
+        assert n_eq >= min(kl, 8), (n_eq, kl, p, q)
+        assert len(set(p.tolist())) == 8
+    ops = fast.operators()
+    gs, loss = fast.grad_s(s, mu, pts, a.LossCfg())
+    torch.cuda.synchronize()
+    l4, rgs = orc.fast_loss(w.net, ops, w.net.s, w.mu[0].astype(np.float64), w.pts, {},
+                            with_grad=True)
+    assert_close(loss.cpu().numpy(), l4, TOL, "fast Q-DEIM r8 loss")
+    assert_close(gs.cpu().numpy(), rgs, TOL, "fast Q-DEIM r8 grad_s")
+    fast.close()
+
+
 def test_fastlrnr_r32_prefix_operators_and_chain():
     """r_hat = 32 on the 64-wide net runs past the resolved snapshot spectrum,
     where POD modes are rounding noise in any precision and later DEIM picks

@@ -306,6 +306,47 @@ def test_deim_interpolation_and_error_bound():
     np.testing.assert_allclose(Xi.T @ Xi, np.eye(8), atol=1e-12)
 
 
+def test_qdeim_equals_pivoted_qr_of_xi_transposed():
+    """Q-DEIM's picks are the first r pivots of LAPACK's column-pivoted QR
+    of Xi^T (scipy.linalg.qr, geqp3), an independent implementation."""
+    from scipy.linalg import qr
+    rng = np.random.default_rng(11)
+    for M, r in ((30, 8), (64, 32), (40, 20)):
+        Z = rng.standard_normal((M, 3 * M))
+        Xi = orc.pod_basis(Z, r)
+        P = orc.qdeim_indices(Xi)
+        piv = qr(Xi.T, pivoting=True)[2][:r]
+        assert list(P) == list(piv), (M, r, P, piv)
+        assert len(set(P.tolist())) == r
+
+
+def test_qdeim_permuted_diagonal_picks_rows_by_norm():
+    """Rows of distinct norms along distinct coordinates: the pivots are the
+    rows in decreasing norm, whatever their order in Xi."""
+    Xi = np.zeros((9, 4))
+    for p, v, k in ((6, 5.0, 0), (1, 4.0, 1), (8, 3.0, 2), (3, 2.0, 3)):
+        Xi[p, k] = v
+    assert list(orc.qdeim_indices(Xi)) == [6, 1, 8, 3]
+
+
+def test_qdeim_interpolation_and_error_bound():
+    rng = np.random.default_rng(12)
+    Z = rng.standard_normal((30, 12)) @ rng.standard_normal((12, 200))
+    Z += 1e-3 * rng.standard_normal(Z.shape)
+    Xi = orc.pod_basis(Z, 8)
+    P = orc.qdeim_indices(Xi)
+    proj = Xi @ np.linalg.inv(Xi[P, :])
+    f = rng.standard_normal(30)
+    np.testing.assert_allclose((proj @ f[P])[P], f[P], rtol=1e-12, atol=1e-12)
+    err = np.linalg.norm(f - proj @ f[P])
+    bound = np.linalg.norm(np.linalg.inv(Xi[P, :]), 2) * np.linalg.norm(f - Xi @ (Xi.T @ f))
+    assert err <= bound * (1 + 1e-10)
+    # Q-DEIM's guarantee: ||(P^T Xi)^{-1}||_2 <= sqrt(M - r + 1) * sqrt(4^r + 6 r - 1) / 3
+    M, r = Xi.shape
+    g = np.linalg.norm(np.linalg.inv(Xi[P, :]), 2)
+    assert g <= np.sqrt(M - r + 1) * np.sqrt(4.0 ** r + 6 * r - 1) / 3
+
+
 def test_fastlrnr_full_index_set_is_lrnr():
     net, pts, mu = tiny_case(M=(2, 12, 10, 9, 1), n=30)
     rng = np.random.default_rng(1)
