@@ -266,6 +266,127 @@ def run_equal_accuracy(args, torch, api, wl, big):
     }
 
 
+def run_reference(args, torch, api, wl, big):
+    """Error against wall time (the Section 4 comparison of Fig. 3): 20 test
+    parameters (10 from each domain of Section 4), the FP64 reference solution
+    of eq. 4.1 on the device (lrnr_cdr_reference: 256 grid points, 1000 Strang
+    steps, 101 output times on t in [0, 1]); for every case whose solution
+    stays bounded, Adam (lr 1e-3) on s from s_init with the LRNR gradient and,
+    separately, with the FastLRNR gradient (built once from snapshots at s_init
+    and, on the small net, 7 perturbed copies), 400 steps each; every 20 steps the L1 relative
+    error of the LRNR at the current s on the reference grid (lrnr_l1_error),
+    against the summed step time (HIP events; evaluation outside it)."""
+    n_x, n_t, n_out, n_steps, every = 256, 1000, 101, 400, 20
+    w = wl.equal_accuracy_case(big=big)
+    net = api.DeviceNet.from_net(w.net)
+    s_init = torch.tensor(w.net.s_flat(), device="cuda")
+    pts = api.DevicePoints.from_points(w.pts)
+    cfg = api.LossCfg()
+    mus = wl.cdr_test_cases()
+    mu_d = torch.tensor(mus, device="cuda")
+    api.cdr_reference(mu_d, n_x, n_t, n_out)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(5):
+        u_ref, st = api.cdr_reference(mu_d, n_x, n_t, n_out)
+    ev1.record()
+    torch.cuda.synchronize()
+    solve_ms = ev0.elapsed_time(ev1) / 5
+    st = st.cpu().numpy()
+    # throughput: 1024 instances (512 per domain) in one launch
+    mu_big = torch.tensor(wl.cdr_test_cases(6, 512, 512), device="cuda")
+    api.cdr_reference(mu_big, n_x, n_t, n_out)
+    ev0.record()
+    for _ in range(3):
+        api.cdr_reference(mu_big, n_x, n_t, n_out)
+    ev1.record()
+    torch.cuda.synchronize()
+    solve_ms_1024 = ev0.elapsed_time(ev1) / 3
+    rng = np.random.Generator(np.random.PCG64(11))
+    s0 = w.net.s_flat()
+    n_pert = 0 if big else 7   # the wide net's POD would take ~40 s on 8 snapshot sets
+    snaps = [s0] + [(s0 * (1.0 + 0.1 * rng.standard_normal(s0.shape))).astype(np.float32)
+                    for _ in range(n_pert)]
+    fast = api.FastLRNR(net, torch.tensor(np.stack(snaps), device="cuda"),
+                        torch.tensor(w.extra["xt_snap"], device="cuda"), w.extra["r_hat"])
+    xt = torch.tensor(wl.grid_points(n_x, n_out), device="cuda")
+    ws_t = api.Workspace()
+    sums = torch.empty(2, dtype=torch.float64, device="cuda")
+
+    def l1(s, ref):
+        u = api.forward_value(net, s, xt)
+        api.l1_error_sums(u, ref, out=sums)
+        a, b = sums.cpu().numpy()
+        return float(a / b)
+
+    def train(grad_fn, ref):
+        s = s_init.clone()
+        m, v = torch.zeros_like(s), torch.zeros_like(s)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(n_steps)]
+        errs, ms, acc = [l1(s, ref)], [0.0], []
+        for k in range(1, n_steps + 1):
+            evs[k - 1][0].record()
+            g = grad_fn(s)
+            api.adam_step(s, m, v, g, k)
+            evs[k - 1][1].record()
+            if k % every == 0:
+                errs.append(l1(s, ref))
+        torch.cuda.synchronize()
+        t = np.cumsum([a.elapsed_time(b) for a, b in evs])
+        ms += [float(t[k - 1]) for k in range(every, n_steps + 1, every)]
+        return errs, ms
+
+    cases = []
+    for i, mu in enumerate(mus):
+        if st[i]:
+            cases.append({"mu": mu.tolist(), "blow_up_step": int(st[i])})
+            continue
+        ref = u_ref[i].reshape(-1)
+        mu32 = torch.tensor(mu.astype(np.float32), device="cuda")
+        lg = lambda s: api.grad_s(net, s, mu32, pts, cfg, with_b=False, ws=ws_t)[0]
+        fg = lambda s: fast.grad_s(s, mu32, pts, cfg, ws=ws_t)[0]
+        if not cases:
+            train(lg, ref)
+            train(fg, ref)
+        el, tl = train(lg, ref)
+        ef, tf = train(fg, ref)
+        # time LRNR needs to reach FastLRNR's best error
+        best_f = min(ef)
+        k_l = next((k for k, e in enumerate(el) if e <= best_f), None)
+        cases.append({
+            "mu": mu.tolist(), "l1_init": el[0],
+            "lrnr_l1": el, "lrnr_ms": tl, "fastlrnr_l1": ef, "fastlrnr_ms": tf,
+            "lrnr_l1_final": el[-1], "fastlrnr_l1_best": best_f,
+            "fastlrnr_ms_to_best": tf[int(np.argmin(ef))],
+            "lrnr_ms_to_fast_best": tl[k_l] if k_l is not None else None,
+        })
+    fast.close()
+    M = w.net.M
+    run = [c for c in cases if "lrnr_l1" in c]
+    return {
+        "net": f"{len(M) - 2} hidden x {M[1]} wide, rank {max(w.net.r)}",
+        "r_hat": w.extra["r_hat"], "n_train": pts.counts[0], "snapshot_sets": 1 + n_pert,
+        "reference": {"n_x": n_x, "n_t": n_t, "n_out": n_out, "instances": len(mus),
+                      "ms_per_solve_batch": solve_ms,
+                      "ms_per_solve_batch_1024": solve_ms_1024,
+                      "instances_per_s_1024": 1024 / (solve_ms_1024 * 1e-3),
+                      "blown_up": int(np.count_nonzero(st))},
+        "cases": cases,
+        "fast_better_or_equal_at_end": sum(1 for c in run if c["fastlrnr_l1"][-1] <= c["lrnr_l1"][-1]),
+        "n_run": len(run),
+    }
+
+
+def cpu_reference_solver(wl):
+    """The oracle's reference solver on the same 20 test parameters (numpy FFT
+    Strang splitting, FP64), one pass."""
+    from oracle import cdr_reference as cdr
+    t = time.time()
+    cdr.cdr_solve_batch(wl.cdr_test_cases(), 256, 1000, 101)
+    return (time.time() - t) * 1e3
+
+
 def run_differentiation(args, torch, api, wl):
     """Differentiation form: 64 instances x 16384 points (own mu and points),
     FastLRNR r_hat = 32 on the small net, CDRLoss (loss kernel forward,
@@ -447,6 +568,7 @@ def main():
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-fidelity", action="store_true")
+    ap.add_argument("--no-reference", action="store_true")
     ap.add_argument("--serve-rates", type=lambda x: [float(v) for v in x.split(",")],
                     default=[50, 100, 200, 500, 1000, 2000])
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -509,12 +631,16 @@ def main():
     if not args.no_equal_acc:
         out["equal_accuracy"] = [run_equal_accuracy(args, torch, api, wl, big)
                                  for big in (False, True)]
+    if not args.no_reference:
+        out["reference"] = [run_reference(args, torch, api, wl, big) for big in (False, True)]
     if not args.no_diff:
         out["differentiation"] = run_differentiation(args, torch, api, wl)
     if not args.no_serve:
         out["serving"] = run_serving(args, torch, api, wl)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(r["w"], wl)
+        if "reference" in out:
+            out["reference"][0]["reference"]["cpu_oracle_ms"] = cpu_reference_solver(wl)
     print(json.dumps(out), flush=True)
 
 

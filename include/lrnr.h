@@ -397,6 +397,40 @@ int32_t lrnr_adam_step(float* s, float* m, float* v, const float* g, int64_t n,
  */
 int32_t lrnr_time_next_fused(void* start_event, void* stop_event);
 
+/*
+ * Reference solution of the convection-diffusion-reaction problem of
+ * Section 4, eq. 4.1 (u_t + mu_1 u_x - mu_2 u_xx - mu_3 u (1 - u) = 0 on
+ * (0, 2 pi) periodic, u(x, 0) = sin x), for B parameter instances at once:
+ * the reference against which the test-accuracy comparison of Section 4
+ * measures L1 relative errors.  The paper names no solver; this one is
+ * Strang splitting R(dt/2) L(dt) R(dt/2) with both sub-flows exact (L in
+ * Fourier space on the uniform grid x_j = 2 pi j / n_x, R the logistic
+ * flow), FP64, dt = t_end / n_t, second order in dt.
+ *  mu     [dev] [B][3]           (beta, nu, rho) per instance, FP64
+ *  u      [dev] [B][n_out][n_x]  out, FP64: u(x_j, t_k), t_k = k t_end / (n_out - 1)
+ *  status [dev] [B]              out: 0, or the 1-based step n at which the
+ *                                instance blew up (a logistic sub-flow left R,
+ *                                or |u| > 1e6 or not finite); u is then NaN
+ *                                at every output time at or after step n.
+ * n_x is a power of two in [8, 1024]; n_out >= 2 and (n_out - 1) divides n_t.
+ * One workgroup per instance; B = 0 is a no-op.  LRNR_EINVAL on bad sizes or
+ * NULL pointers.  Asynchronous on the stream; no workspace.
+ */
+int32_t lrnr_cdr_reference(const double* mu, int32_t B, int32_t n_x, int32_t n_t,
+                           int32_t n_out, double t_end, double* u, int32_t* status,
+                           void* stream);
+
+/*
+ * L1 relative error of a prediction against a reference (the error measure of
+ * the Section 4 comparison), as two FP64 sums taken in a fixed order:
+ *  pred [dev] [n] FP32 (e.g. lrnr_forward_value on the reference grid)
+ *  ref  [dev] [n] FP64
+ *  out  [dev] [2] out: sum |pred - ref|, sum |ref|  (error = out[0] / out[1])
+ * Results are bitwise reproducible.  n may be 0 (both sums 0).
+ */
+int32_t lrnr_l1_error(const float* pred, const double* ref, int64_t n, double* out,
+                      void* stream);
+
 /* Text of a status code (thread-local detail for LRNR_EHIP / LRNR_EINVAL). */
 const char* lrnr_status_string(int32_t status);
 

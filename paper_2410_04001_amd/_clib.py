@@ -136,6 +136,8 @@ SIGNATURES = {
     "fastlrnr_destroy": (I32, [P]),
     "lrnr_adam_step": (I32, [P, P, P, P, I64, I32, F32, F32, F32, F32, P]),
     "lrnr_time_next_fused": (I32, [P, P]),
+    "lrnr_cdr_reference": (I32, [P, I32, I32, I32, I32, C.c_double, P, P, P]),
+    "lrnr_l1_error": (I32, [P, P, I64, P, P]),
     "lrnr_status_string": (C.c_char_p, [I32]),
 }
 

@@ -319,6 +319,35 @@ def adam_step(s, m, v, g, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
                                      _stream()), "lrnr_adam_step")
 
 
+def cdr_reference(mu, n_x, n_t, n_out, t_end=1.0):
+    """Reference solution of eq. 4.1 for mu [B][3] (float64 device tensor) by
+    lrnr_cdr_reference: returns (u [B][n_out][n_x] float64, status [B] int32),
+    both on the device."""
+    mu = mu.contiguous()
+    if mu.dtype != torch.float64 or mu.dim() != 2 or mu.shape[1] != 3:
+        raise ValueError("mu must be a float64 [B][3] tensor")
+    B = mu.shape[0]
+    u = torch.empty(B, n_out, n_x, dtype=torch.float64, device=mu.device)
+    st = torch.empty(B, dtype=torch.int32, device=mu.device)
+    cl.check(cl.lib().lrnr_cdr_reference(_p(mu), B, int(n_x), int(n_t), int(n_out),
+                                          float(t_end), _p(u), _p(st), _stream()),
+             "lrnr_cdr_reference")
+    return u, st
+
+
+def l1_error_sums(pred, ref, out=None):
+    """(sum |pred - ref|, sum |ref|) as a float64 [2] device tensor
+    (lrnr_l1_error); pred float32, ref float64, same number of elements."""
+    pred, ref = pred.contiguous(), ref.contiguous()
+    if pred.dtype != torch.float32 or ref.dtype != torch.float64 or pred.numel() != ref.numel():
+        raise ValueError("pred float32 and ref float64 of the same size")
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=ref.device)
+    cl.check(cl.lib().lrnr_l1_error(_p(pred), _p(ref), pred.numel(), _p(out), _stream()),
+             "lrnr_l1_error")
+    return out
+
+
 class FastLRNR:
     """A FastLRNR built on the device by fastlrnr_build (eq. 2.7); its reduced
     net runs through the same entry points as the LRNR."""

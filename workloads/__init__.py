@@ -224,6 +224,17 @@ def instances_case(seed: int = 3, n_inst: int = 64, n: int = 16384) -> Workload:
     return Workload(net, per[0], mu, extra={"xt_snap": xt_snap, "r_hat": 32, "pts": per})
 
 
+def cdr_test_cases(seed: int = 5, n1: int = 10, n2: int = 10) -> np.ndarray:
+    """Test parameters of the Section 4 comparison, float64 [n1 + n2][3]:
+    n1 draws from the pure-convection domain [5, 8] x {0} x {0}, then n2 from
+    the convection-diffusion-reaction domain [1, 3] x [0, 2] x [0, 2]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d1 = np.stack([rng.uniform(5.0, 8.0, n1), np.zeros(n1), np.zeros(n1)], axis=1)
+    d2 = np.stack([rng.uniform(1.0, 3.0, n2), rng.uniform(0.0, 2.0, n2),
+                   rng.uniform(0.0, 2.0, n2)], axis=1)
+    return np.concatenate([d1, d2])
+
+
 def serving_stream(seed: int = 4, n_req: int = 2000, rate: float = 500.0):
     """Poisson stream of new-mu requests: arrival times (s), mu, point counts
     log-uniform in [1024, 65536], reduced widths drawn from {16, 32, 48}, and a
