@@ -24,6 +24,7 @@ Paper passages followed (arXiv 2410.04001):
   * Section 4, eq. (4.1): N[u; mu] = u_t + mu_1 u_x - mu_2 u_xx - mu_3 u (1 - u),
     u(x, 0) = sin x, u(0, t) = u(2 pi, t).
   * sigma = sin (the paper leaves sigma open; the workload fixes it).
+  * Section 2.1 (remark on the biases): factored biases b^l = B^l s_b^l.
 
 The two networks are computed by two different routes on purpose: LRNR by the
 dense route (form W^l explicitly, run eq. 2.1), FastLRNR by the reduced chain
@@ -466,6 +467,69 @@ def fast_loss(net, fast, s_list, mu, pts, cfg=None, with_grad=False):
     gs, _ = fast_backward(net, fast, s_list, cache, ubar)
     gs = [g + h for g, h in zip(gs, gloc)]
     return loss4, np.concatenate(gs)
+
+
+# --------------------------------------------------------------------------
+# Factored biases (the variant the paper notes in Section 2.1 and does not
+# use: the bias treated like the weights, so that it is driven by
+# coefficients too).  Reading: b^l = B^l s_b^l with a basis B^l [M_l][q_l]
+# and coefficients s_b^l [q_l]; the rest of the network is unchanged, so the
+# gradient to s_b follows from the bias gradient by the chain rule.
+# --------------------------------------------------------------------------
+
+def bias_from_basis(B_list, sb_list):
+    """b^l = B^l s_b^l for every layer."""
+    return [_f(B) @ _f(sb) for B, sb in zip(B_list, sb_list)]
+
+
+def _split(v, sizes):
+    out, o = [], 0
+    for n in sizes:
+        out.append(v[o:o + n])
+        o += n
+    return out
+
+
+def lrnr_loss_factored_bias(net, s_list, B_list, sb_list, mu, pts, cfg=None, with_grad=False):
+    """LRNR loss with factored biases; returns (loss4, grad_s, grad_sb) with
+    grad_sb^l = B^lT (dL/db^l), flat over layers."""
+    import copy
+    n2 = copy.copy(net)
+    n2.b = bias_from_basis(B_list, sb_list)
+    loss4, gs, gb = lrnr_loss(n2, s_list, mu, pts, cfg, with_grad)
+    if not with_grad:
+        return loss4, None, None
+    gbl = _split(gb, [len(x) for x in n2.b])
+    gsb = np.concatenate([_f(B).T @ g for B, g in zip(B_list, gbl)])
+    return loss4, gs, gsb
+
+
+def fast_loss_factored_bias(net, fast, s_list, B_list, sb_list, mu, pts, cfg=None,
+                            with_grad=False):
+    """FastLRNR loss with factored biases: the reduced bias of hidden layer l
+    is P^lT B^l s_b^l (the rows of the basis at the interpolation indices,
+    eq. 2.7 applied to b = B s_b), the output bias B^L s_b^L; returns
+    (loss4, grad_s, grad_sb)."""
+    import copy
+    L = net.L
+    Bh = [_f(B_list[l])[np.asarray(fast["P"][l]), :] for l in range(L - 1)] + [_f(B_list[L - 1])]
+    bh = bias_from_basis(Bh, sb_list)
+    f2 = dict(fast)
+    f2["b_hat"] = bh[:L - 1]
+    n2 = copy.copy(net)
+    n2.b = list(net.b[:L - 1]) + [bh[L - 1]]
+    cfg = cfg or {}
+    X, n_r, n_0, n_b = _all_points(pts)
+    jets, cache = fast_forward(n2, f2, s_list, X)
+    terms, ubar = _loss_and_ubar(jets, n_r, n_0, n_b, _f(pts.x_0), mu, cfg)
+    loc, gloc = _loc_term(s_list, cfg)
+    loss4 = np.array([terms[0] + terms[1] + terms[2] + loc] + terms)
+    if not with_grad:
+        return loss4, None, None
+    gs, gb = fast_backward(n2, f2, s_list, cache, ubar)
+    gs = [g + h for g, h in zip(gs, gloc)]
+    gsb = np.concatenate([B.T @ g for B, g in zip(Bh, gb)])
+    return loss4, np.concatenate(gs), gsb
 
 
 # --------------------------------------------------------------------------

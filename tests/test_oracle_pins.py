@@ -388,6 +388,63 @@ def test_fastlrnr_jets_complex_step():
                                rtol=1e-12, atol=1e-14)
 
 
+# ------------------------------------------------------ factored biases -----
+
+def _bias_basis(net, q, seed=5):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    B = [rng.standard_normal((m, min(q, m))) / math.sqrt(m) for m in net.M[1:]]
+    sb = [rng.uniform(-1, 1, b.shape[1]) for b in B]
+    return B, sb
+
+
+def test_factored_bias_identity_basis_is_the_plain_bias():
+    # B^l = I, s_b^l = b^l: same loss, and grad_sb equals grad_b
+    net, pts, mu = tiny_case(n=25)
+    cfg = {"form": 0, "w_r": 1.0, "w_0": 1.0, "w_b": 1.0}
+    B = [np.eye(len(b)) for b in net.b]
+    l_a, gs_a, gb_a = orc.lrnr_loss(net, net.s, mu, pts, cfg, with_grad=True)
+    l_b, gs_b, gsb = orc.lrnr_loss_factored_bias(net, net.s, B, net.b, mu, pts, cfg, True)
+    np.testing.assert_allclose(l_b, l_a, rtol=1e-14)
+    np.testing.assert_allclose(gs_b, gs_a, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(gsb, gb_a, rtol=1e-13, atol=1e-15)
+
+
+def test_factored_bias_grad_complex_step():
+    net, pts, mu = tiny_case(n=25)
+    cfg = {"form": 0, "w_r": 1.0, "w_0": 1.0, "w_b": 1.0}
+    B, sb = _bias_basis(net, 3)
+    _, gs, gsb = orc.lrnr_loss_factored_bias(net, net.s, B, sb, mu, pts, cfg, True)
+    q = [len(x) for x in sb]
+    sb0 = np.concatenate(sb)
+    c = _complex_step_grad(lambda z: orc.lrnr_loss_factored_bias(
+        net, net.s, B, orc._split(z, q), mu, pts, cfg)[0][0], sb0)
+    np.testing.assert_allclose(gsb, c, rtol=1e-11, atol=1e-14)
+    cs = _complex_step_grad(lambda z: orc.lrnr_loss_factored_bias(
+        net, net.split_s(z), B, sb, mu, pts, cfg)[0][0], net.s_flat().astype(np.float64))
+    np.testing.assert_allclose(gs, cs, rtol=1e-11, atol=1e-14)
+
+
+def test_fastlrnr_factored_bias_full_index_set_and_complex_step():
+    net, pts, mu = tiny_case(M=(2, 12, 10, 9, 1), n=30)
+    rng = np.random.default_rng(1)
+    cfg = {"form": 0, "w_r": 1.0, "w_0": 1.0, "w_b": 1.0}
+    B, sb = _bias_basis(net, 4)
+    q = [len(x) for x in sb]
+    # the index set of every neuron: FastLRNR with factored biases is the LRNR's
+    full = orc.fastlrnr_build(net, [net.s], wl.uniform_points(rng, 64), [12, 10, 9])
+    l_a, gs_a, gsb_a = orc.lrnr_loss_factored_bias(net, net.s, B, sb, mu, pts, cfg, True)
+    l_b, gs_b, gsb_b = orc.fast_loss_factored_bias(net, full, net.s, B, sb, mu, pts, cfg, True)
+    np.testing.assert_allclose(l_b, l_a, rtol=1e-10)
+    np.testing.assert_allclose(gs_b, gs_a, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(gsb_b, gsb_a, rtol=1e-9, atol=1e-12)
+    # a reduced FastLRNR: analytic grad_sb against complex step
+    fast = orc.fastlrnr_build(net, [net.s], wl.uniform_points(rng, 64), [6, 5, 4])
+    _, _, gsb = orc.fast_loss_factored_bias(net, fast, net.s, B, sb, mu, pts, cfg, True)
+    c = _complex_step_grad(lambda z: orc.fast_loss_factored_bias(
+        net, fast, net.s, B, orc._split(z, q), mu, pts, cfg)[0][0], np.concatenate(sb))
+    np.testing.assert_allclose(gsb, c, rtol=1e-11, atol=1e-14)
+
+
 # ---------------------------------------------------------------- Adam -----
 
 def test_adam_closed_form_constant_gradient():
