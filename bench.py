@@ -135,6 +135,46 @@ def run_fast(args, torch, api, wl):
     }
 
 
+def run_factored_bias(args, torch, api, wl):
+    """Factored biases b^l = B^l s_b^l (q = 8 columns per layer, seeded
+    Gaussian basis): loss + grad_s + grad_sb against the plain loss + grad_s,b,
+    on the small net (N = 65536) for the LRNR and the FastLRNR (r_hat = 32),
+    and on the working-size net (N = 262144)."""
+    out = {}
+    for name, w in (("small", wl.fast_case(2)), ("working", wl.big_lrnr(1))):
+        rng = np.random.Generator(np.random.PCG64(5))
+        B = [(rng.standard_normal((m, min(8, m))) / math.sqrt(m)).astype(np.float32)
+             for m in w.net.M[1:]]
+        bb = api.BiasBasis(w.net.M, [b.shape[1] for b in B],
+                           np.concatenate([b.reshape(-1) for b in B]))
+        s_b = torch.tensor(rng.uniform(-1, 1, bb.q_total).astype(np.float32), device="cuda")
+        net = api.DeviceNet.from_net(w.net)
+        s = torch.tensor(w.net.s_flat(), device="cuda")
+        pts = api.DevicePoints.from_points(w.pts)
+        mu = torch.tensor(w.mu[0], device="cuda")
+        cfg = api.LossCfg()
+        ws = api.Workspace()
+        steps = max(20, args.steps)
+        row = {
+            "plain_ms": time_calls(torch, lambda: api.grad_s(net, s, mu, pts, cfg, ws=ws), steps, 5),
+            "factored_ms": time_calls(
+                torch, lambda: api.grad_s_factored(net, bb, s, s_b, mu, pts, cfg, ws=ws), steps, 5),
+            "n_interior": pts.counts[0], "q": bb.q,
+        }
+        if name == "small":
+            fast = api.FastLRNR(net, s.reshape(1, -1),
+                                torch.tensor(w.extra["xt_snap"], device="cuda"), w.extra["r_hat"])
+            red = fast.bias_basis(bb)
+            row["fastlrnr_plain_ms"] = time_calls(
+                torch, lambda: api.grad_s(fast.net, s, mu, pts, cfg, ws=ws), steps, 5)
+            row["fastlrnr_factored_ms"] = time_calls(
+                torch, lambda: api.grad_s_factored(fast.net, red, s, s_b, mu, pts, cfg, ws=ws),
+                steps, 5)
+            fast.close()
+        out[name] = row
+    return out
+
+
 def run_fidelity(args, torch, api, wl):
     """FastLRNR fidelity against the reduced width r_hat (the sweep of
     Fig. 2 (bottom), on a synthetic net): on the small net (64 wide, rank 8)
@@ -569,6 +609,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-fidelity", action="store_true")
     ap.add_argument("--no-reference", action="store_true")
+    ap.add_argument("--no-bias", action="store_true")
     ap.add_argument("--serve-rates", type=lambda x: [float(v) for v in x.split(",")],
                     default=[50, 100, 200, 500, 1000, 2000])
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -626,6 +667,8 @@ def main():
     }
     if fast is not None:
         out["fastlrnr"] = fast
+    if not args.no_bias:
+        out["factored_bias"] = run_factored_bias(args, torch, api, wl)
     if not args.no_fidelity:
         out["fidelity"] = run_fidelity(args, torch, api, wl)
     if not args.no_equal_acc:

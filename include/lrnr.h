@@ -398,6 +398,51 @@ int32_t lrnr_adam_step(float* s, float* m, float* v, const float* g, int64_t n,
 int32_t lrnr_time_next_fused(void* start_event, void* stop_event);
 
 /*
+ * Factored biases.  Section 2.1 notes that the biases can be factored like
+ * the weights (and does not do it); here b^l = B^l s_b^l, so that the biases
+ * too are driven by coefficients s_b while the basis B stays fixed.  A basis:
+ *  L     layers (the net's L)
+ *  M[l]  rows of B^l for l = 1..L (the net's widths; M[0] is not used)
+ *  q[l]  columns of B^l, 0..LRNR_MAX_RANK (q[l] = 0: b^l = 0)
+ *  B     [dev] layers 1..L packed, each [M[l]][q[l]] row-major
+ * Coefficients s_b [sum_l q[l]] and biases b [sum_l M[l]] are packed by layer
+ * (b as lrnr_net.b).  A factored-bias step is lrnr_bias_compose into the b
+ * array the net points at, lrnr_grad_s with grad_b, then lrnr_bias_grad.
+ */
+typedef struct lrnr_bias_basis {
+  int32_t L;
+  int32_t M[LRNR_MAX_LAYERS + 1];
+  int32_t q[LRNR_MAX_LAYERS + 1];
+  const float* B;
+} lrnr_bias_basis;
+
+/* b^l = B^l s_b^l for every layer (FP64 sums over the columns in order):
+ *  s_b [dev] [sum_l q[l]];  b [dev] [sum_l M[l]] out.
+ * LRNR_EINVAL on a bad basis (L, M[l] > LRNR_MAX_WIDTH, q[l]) or NULL arrays. */
+int32_t lrnr_bias_compose(const lrnr_bias_basis* bb, const float* s_b, float* b,
+                          void* stream);
+
+/* Chain rule through the factored bias: grad_sb^l = B^lT grad_b^l (FP64 sums
+ * over the rows in order):
+ *  grad_b [dev] [sum_l M[l]] (from lrnr_grad_s or a GRAD task);
+ *  grad_sb [dev] [sum_l q[l]] out. */
+int32_t lrnr_bias_grad(const lrnr_bias_basis* bb, const float* grad_b, float* grad_sb,
+                       void* stream);
+
+/* The reduced basis of a FastLRNR (eq. 2.7 applied to b = B s_b): for every
+ * hidden layer the rows of B^l at the handle's indices P^l, B_hat^l =
+ * P^lT B^l [r_hat_l][q[l]]; the output layer's B^L unchanged.
+ *  full    basis of the LRNR the handle was built from (M[l] its widths)
+ *  B_hat   [dev] out, sum_{l<L} r_hat_l q[l] + M[L] q[L] floats, caller-owned
+ *  reduced out (host struct, may be NULL): the basis over B_hat with the
+ *          reduced widths, for lrnr_bias_compose / lrnr_bias_grad with the
+ *          net of fastlrnr_get_net (whose b is then replaced by the composed one).
+ * LRNR_EINVAL when L or M[L] differ from the handle's net or an index is not
+ * a row of B^l. */
+int32_t fastlrnr_bias_basis(const fastlrnr_handle* h, const lrnr_bias_basis* full,
+                            float* B_hat, lrnr_bias_basis* reduced, void* stream);
+
+/*
  * Reference solution of the convection-diffusion-reaction problem of
  * Section 4, eq. 4.1 (u_t + mu_1 u_x - mu_2 u_xx - mu_3 u (1 - u) = 0 on
  * (0, 2 pi) periodic, u(x, 0) = sin x), for B parameter instances at once:

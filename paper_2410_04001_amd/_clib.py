@@ -46,6 +46,15 @@ class LrnrLossCfg(C.Structure):
     ]
 
 
+class LrnrBiasBasis(C.Structure):
+    _fields_ = [
+        ("L", C.c_int32),
+        ("M", C.c_int32 * (MAX_LAYERS + 1)),
+        ("q", C.c_int32 * (MAX_LAYERS + 1)),
+        ("B", C.c_void_p),
+    ]
+
+
 SEL_DEIM, SEL_QDEIM = 0, 1  # include/lrnr.h LRNR_SEL_*
 MODE_JETS, MODE_VALUE, MODE_LOSS, MODE_GRAD, MODE_VJP = 0, 1, 2, 3, 4
 
@@ -136,6 +145,9 @@ SIGNATURES = {
     "fastlrnr_destroy": (I32, [P]),
     "lrnr_adam_step": (I32, [P, P, P, P, I64, I32, F32, F32, F32, F32, P]),
     "lrnr_time_next_fused": (I32, [P, P]),
+    "lrnr_bias_compose": (I32, [C.POINTER(LrnrBiasBasis), P, P, P]),
+    "lrnr_bias_grad": (I32, [C.POINTER(LrnrBiasBasis), P, P, P]),
+    "fastlrnr_bias_basis": (I32, [P, C.POINTER(LrnrBiasBasis), P, C.POINTER(LrnrBiasBasis), P]),
     "lrnr_cdr_reference": (I32, [P, I32, I32, I32, I32, C.c_double, P, P, P]),
     "lrnr_l1_error": (I32, [P, P, I64, P, P]),
     "lrnr_status_string": (C.c_char_p, [I32]),

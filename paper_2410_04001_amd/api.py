@@ -319,6 +319,67 @@ def adam_step(s, m, v, g, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
                                      _stream()), "lrnr_adam_step")
 
 
+class BiasBasis:
+    """Factored biases b^l = B^l s_b^l (lrnr_bias_basis): widths M[0..L] of
+    the net, columns q[1..L] and the packed basis B (device float32)."""
+
+    def __init__(self, M, q, B, device="cuda", _keep=None):
+        self.M = [int(m) for m in M]
+        self.q = [int(x) for x in q]
+        self.L = len(self.q)
+        self.B = _dev(B, device) if not isinstance(B, int) else B
+        self._keep = _keep
+        self._c = cl.LrnrBiasBasis()
+        self._c.L = self.L
+        for l, m in enumerate(self.M):
+            self._c.M[l] = m
+        for l, x in enumerate(self.q, start=1):
+            self._c.q[l] = x
+        self._c.B = self.B if isinstance(self.B, int) else self.B.data_ptr()
+
+    @property
+    def q_total(self):
+        return sum(self.q)
+
+    @property
+    def b_total(self):
+        return sum(self.M[1:])
+
+    def c(self):
+        return C.byref(self._c)
+
+
+def bias_compose(bb, s_b, out=None):
+    """b = B s_b per layer (lrnr_bias_compose)."""
+    if out is None:
+        out = torch.empty(bb.b_total, dtype=torch.float32, device=s_b.device)
+    cl.check(cl.lib().lrnr_bias_compose(bb.c(), _p(s_b), _p(out), _stream()),
+             "lrnr_bias_compose")
+    return out
+
+
+def bias_grad(bb, grad_b):
+    """grad_sb^l = B^lT grad_b^l (lrnr_bias_grad)."""
+    g = torch.empty(bb.q_total, dtype=torch.float32, device=grad_b.device)
+    cl.check(cl.lib().lrnr_bias_grad(bb.c(), _p(grad_b), _p(g), _stream()), "lrnr_bias_grad")
+    return g
+
+
+def with_bias(net, b):
+    """The same net (U, V shared) with its biases taken from the tensor b."""
+    U = net.U if isinstance(net.U, int) else net.U.data_ptr()
+    V = net.V if isinstance(net.V, int) else net.V.data_ptr()
+    return DeviceNet(net.M, net.r, U, V, b.data_ptr(), _keep=(net, b))
+
+
+def grad_s_factored(net, bb, s, s_b, mu, pts, cfg, ws=None):
+    """Loss and gradients to s and s_b of the net with factored biases:
+    lrnr_bias_compose, lrnr_grad_s (with grad_b), lrnr_bias_grad."""
+    b = bias_compose(bb, s_b)
+    gs, gb, loss = grad_s(with_bias(net, b), s, mu, pts, cfg, with_b=True, ws=ws)
+    return gs, bias_grad(bb, gb), loss
+
+
 def cdr_reference(mu, n_x, n_t, n_out, t_end=1.0):
     """Reference solution of eq. 4.1 for mu [B][3] (float64 device tensor) by
     lrnr_cdr_reference: returns (u [B][n_out][n_x] float64, status [B] int32),
@@ -409,6 +470,18 @@ class FastLRNR:
         cl.check(cl.lib().fastlrnr_grad_s(self._h, _p(s), _p(mu), pts.c(), cfg.c(), _p(gs),
                                           _p(loss), wp, wn, _stream()), "fastlrnr_grad_s")
         return gs, loss
+
+    def bias_basis(self, full):
+        """The reduced basis (fastlrnr_bias_basis): rows of the full basis at
+        the indices P, as a BiasBasis over the reduced widths."""
+        n = self.net
+        # a basis of another depth is rejected by the library (LRNR_EINVAL)
+        nB = sum(n.M[l] * full.q[l - 1] for l in range(1, min(n.L, full.L) + 1))
+        Bh = torch.empty(max(nB, 1), dtype=torch.float32, device=full.B.device)
+        red = cl.LrnrBiasBasis()
+        cl.check(cl.lib().fastlrnr_bias_basis(self._h, full.c(), _p(Bh), C.byref(red), _stream()),
+                 "fastlrnr_bias_basis")
+        return BiasBasis(n.M, full.q, Bh)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -19,6 +19,7 @@ struct fastlrnr_handle {
   float* U = nullptr;
   float* V = nullptr;
   float* b = nullptr;
+  int32_t* Pd = nullptr;  // device copy of P
   std::vector<int32_t> P; // concatenated indices of hidden layers 1..L-1
 };
 
@@ -576,8 +577,8 @@ done:
   (void)hipFree(A);
   (void)hipFree(R);
   (void)hipFree(rank);
-  (void)hipFree(Pd);
   (void)hipFree(status);
+  h->Pd = Pd;
   if (rc != LRNR_OK) {
     fastlrnr_destroy(h);
     return rc;
@@ -624,11 +625,19 @@ int32_t fastlrnr_grad_s(const fastlrnr_handle* h, const float* s, const float* m
   return lrnr_grad_s(&h->net, s, mu, pts, cfg, grad_s, nullptr, loss, ws, ws_bytes, stream);
 }
 
+int32_t fastlrnr_bias_basis(const fastlrnr_handle* h, const lrnr_bias_basis* full, float* B_hat,
+                            lrnr_bias_basis* reduced, void* stream) {
+  if (!h) return fail(LRNR_EINVAL, "NULL handle");
+  return bias_gather(full, h->P.data(), h->Pd, &h->net, B_hat, reduced,
+                     static_cast<hipStream_t>(stream));
+}
+
 int32_t fastlrnr_destroy(fastlrnr_handle* h) {
   if (!h) return LRNR_EINVAL;
   (void)hipFree(h->U);
   (void)hipFree(h->V);
   (void)hipFree(h->b);
+  (void)hipFree(h->Pd);
   delete h;
   return LRNR_OK;
 }
