@@ -179,8 +179,8 @@ def run_fidelity(args, torch, api, wl):
     """FastLRNR fidelity against the reduced width r_hat (the sweep of
     Fig. 2 (bottom), on a synthetic net): on the small net (64 wide, rank 8)
     with the 65536 training points of the FastLRNR comparison, the FastLRNR
-    loss and grad_s against the LRNR's at the same s, and u at 16384 held-out
-    points, for DEIM and Q-DEIM index selection, each from snapshots at s
+    loss and grad_s against the LRNR's at the same s, and u and the reduced
+    states z_hat^l (against V^{(l+1)T} z^l) at 16384 held-out points, for DEIM and Q-DEIM index selection, each from snapshots at s
     alone and at s plus 7 perturbed copies (each entry scaled by
     1 + 0.1 N(0, 1)); with the build time and the FastLRNR loss+grad time."""
     import numpy as np
@@ -199,6 +199,7 @@ def run_fidelity(args, torch, api, wl):
     snaps = {"s": s.reshape(1, -1), "s + 7 perturbed": torch.tensor(np.stack(pert), device="cuda")}
     gs_l, _, loss_l = api.grad_s(net, s, mu, pts, cfg, with_b=False)
     u_l = api.forward_value(net, s, xt_held)
+    y_l = [y.double() for y in api.reduced_states(net, s, xt_held)]
     ms_l = time_calls(torch, lambda: api.grad_s(net, s, mu, pts, cfg, with_b=False), 20, 3)
     torch.cuda.synchronize()
     gl = gs_l.double()
@@ -221,6 +222,8 @@ def run_fidelity(args, torch, api, wl):
                     "grad_cosine": float((gf @ gl) / (gf.norm() * gl.norm())),
                     "loss_rel_err": float(abs(loss_f[0].double() - loss_l[0].double()) / loss_l[0].double()),
                     "u_heldout_rel_err": float((u_f.double() - u_l.double()).norm() / u_l.double().norm()),
+                    "state_rel_err": [float((yf.double() - yl).norm() / yl.norm()) for yf, yl in
+                                      zip(api.reduced_states(fast.net, s, xt_held), y_l)],
                     "build_ms": build_ms, "fastlrnr_grad_ms": ms_f, "lrnr_grad_ms": ms_l,
                 })
                 fast.close()

@@ -117,6 +117,19 @@ int32_t lrnr_forward_value(const lrnr_net* net, const float* s, const float* xt,
                            int64_t n, float* u, void* stream);
 
 /*
+ * Reduced states (values only): for every hidden layer l = 1..L-1 the
+ * r_{l+1} coordinates y^{l+1} = V^{(l+1)T} z^l of z^l = sigma(U^l (s^l * y^l)
+ * + b^l) at each point.  On the net of fastlrnr_get_net these are the reduced
+ * states z_hat^l of eq. 2.8; on the LRNR, the V^{(l+1)T} z^l they approximate
+ * (Section 2.2), so the two calls give the FastLRNR's state error.
+ *  xt [dev] [n][2];  y [dev] [sum_{l=2..L} r[l]][n] out (layer by layer,
+ *  coordinate-major).  FP32, one thread per point (a diagnostic, not the hot
+ *  path).  n may be 0.
+ */
+int32_t lrnr_reduced_states(const lrnr_net* net, const float* s, const float* xt, int64_t n,
+                            float* y, void* stream);
+
+/*
  * Workspace bytes needed by lrnr_residual_loss / lrnr_grad_s for this net and
  * these point counts (batch = number of instances; 1 for the single calls).
  * Returns 0 when the net or counts are invalid.

@@ -123,6 +123,7 @@ TASKP = C.POINTER(LrnrTask)
 SIGNATURES = {
     "lrnr_forward_jets": (I32, [NETP, P, P, I64, P, P]),
     "lrnr_forward_value": (I32, [NETP, P, P, I64, P, P]),
+    "lrnr_reduced_states": (I32, [NETP, P, P, I64, P, P]),
     "lrnr_workspace_size": (SZ, [NETP, PTSP, I32]),
     "lrnr_residual_loss": (I32, [NETP, P, P, PTSP, CFGP, P, P, SZ, P]),
     "lrnr_grad_s": (I32, [NETP, P, P, PTSP, CFGP, P, P, P, P, SZ, P]),

@@ -152,6 +152,17 @@ def forward_value(net, s, xt):
     return out
 
 
+def reduced_states(net, s, xt):
+    """y^{l+1} = V^{(l+1)T} z^l of every hidden layer at the points xt
+    (lrnr_reduced_states): a list of [r_{l+1}][n] tensors, l = 1..L-1."""
+    n = xt.shape[0]
+    rows = net.r[1:]
+    y = torch.empty((sum(rows), n), dtype=torch.float32, device=xt.device)
+    cl.check(cl.lib().lrnr_reduced_states(net.c(), _p(s), _p(xt), n, _p(y), _stream()),
+             "lrnr_reduced_states")
+    return list(torch.split(y, rows, dim=0))
+
+
 def residual_loss(net, s, mu, pts, cfg, ws=None):
     ws = ws or _ws(s.device)
     wp, wn = ws.ptr_size(workspace_size(net, pts))
