@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "lrnr_internal.h"
+#include "lrnr_bias.h"
 
 struct fastlrnr_handle {
   lrnr_net net;           // reduced net; U, V, b point at the buffers below

@@ -7,7 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "lrnr_internal.h"
+#include "lrnr_bias.h"
 
 namespace lrnr {
 namespace {

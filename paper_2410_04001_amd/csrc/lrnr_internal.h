@@ -173,12 +173,6 @@ hipError_t launch_reduce(const KReduce& kr, hipStream_t stream);
 // Detail text returned by lrnr_status_string for the calling thread.
 void set_status_detail(const char* text);
 
-// Reduced bias basis of a FastLRNR (csrc/lrnr_bias.hip): rows of the full
-// basis at the indices P (host copy for the checks, device copy for the gather).
-int32_t bias_gather(const lrnr_bias_basis* full, const int32_t* P_host, const int32_t* P_dev,
-                    const lrnr_net* reduced_net, float* B_hat, lrnr_bias_basis* reduced,
-                    hipStream_t stream);
-
 // ---- host-side validation shared by the entry points (set the detail text) ----
 int32_t fail(int32_t code, const char* fmt, ...);
 int32_t hip_fail(hipError_t e, const char* where);
