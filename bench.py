@@ -78,7 +78,24 @@ def run_lrnr(args, torch, api, wl):
     flops, per_pt = algorithmic_flops(w.net.M, w.net.r, n_r, n_0 + 2 * n_b)
     kavg = float(np.mean(kern_ms))
     achieved = flops / (kavg * 1e-3) / 1e12
+    # the same step at each of the workload's 8 parameter draws (own s, m, v)
+    per_mu = []
+    for j in range(len(w.mu)):
+        mu_j = torch.tensor(w.mu[j], device="cuda")
+        s_j = torch.tensor(w.net.s_flat(), device="cuda")
+        m_j, v_j = torch.zeros_like(s_j), torch.zeros_like(s_j)
+        it = [0]
+
+        def step_j():
+            it[0] += 1
+            g, _, _ = api.grad_s(net, s_j, mu_j, pts, cfg, with_b=True, ws=ws)
+            api.adam_step(s_j, m_j, v_j, g, it[0])
+
+        ms_j = time_calls(torch, step_j, 10, 3)
+        per_mu.append({"mu": [float(x) for x in w.mu[j]], "ms_per_step": ms_j,
+                       "pts_per_s": n_r / (ms_j * 1e-3)})
     return {
+        "per_mu": per_mu,
         "ms_per_step": total_ms / args.steps,
         "pts_per_s": n_r / (total_ms / args.steps * 1e-3),
         "kernel_ms_avg": kavg,
@@ -389,7 +406,7 @@ def run_reference(args, torch, api, wl, big):
         mu32 = torch.tensor(mu.astype(np.float32), device="cuda")
         lg = lambda s: api.grad_s(net, s, mu32, pts, cfg, with_b=False, ws=ws_t)[0]
         fg = lambda s: fast.grad_s(s, mu32, pts, cfg, ws=ws_t)[0]
-        if not cases:
+        if not any("lrnr_l1" in c for c in cases):   # warm both loops once
             train(lg, ref)
             train(fg, ref)
         el, tl = train(lg, ref)
@@ -668,6 +685,7 @@ def main():
             "flops_per_launch": r["flops_per_launch"],
         },
     }
+    out["per_mu"] = r["per_mu"]
     if fast is not None:
         out["fastlrnr"] = fast
     if not args.no_bias:

@@ -25,6 +25,8 @@ Paper passages followed (arXiv 2410.04001):
     u(x, 0) = sin x, u(0, t) = u(2 pi, t).
   * sigma = sin (the paper leaves sigma open; the workload fixes it).
   * Section 2.1 (remark on the biases): factored biases b^l = B^l s_b^l.
+  * Section 3.1, eq. (3.1)-(3.4): hypernetwork s = f_hyper(mu; Theta), meta
+    loss over parameter samples, R_sparse (bases held fixed).
 
 The two networks are computed by two different routes on purpose: LRNR by the
 dense route (form W^l explicitly, run eq. 2.1), FastLRNR by the reduced chain
@@ -530,6 +532,107 @@ def fast_loss_factored_bias(net, fast, s_list, B_list, sb_list, mu, pts, cfg=Non
     gs = [g + h for g, h in zip(gs, gloc)]
     gsb = np.concatenate([B.T @ g for B, g in zip(Bh, gb)])
     return loss4, np.concatenate(gs), gsb
+
+
+# --------------------------------------------------------------------------
+# Meta-learning of the coefficient map (Section 3.1, eq. 3.1-3.4) with the
+# bases U, V, b held fixed: the hypernetwork s = f_hyper(mu; Theta), the meta
+# loss averaged over parameter samples and the sparsity term R_sparse.
+# Readings: f_hyper is a network of the form of eq. 2.1 with the same
+# activation sigma = sin and a ReLU on its output; Theta is packed per layer
+# as W_k [H_k][H_{k-1}] row-major, then c_k [H_k]; the sigma inside R_sparse is
+# the ReLU; expectations over mu are means over the sample.
+# --------------------------------------------------------------------------
+
+def _relu(x):
+    return np.where(np.real(x) > 0, x, 0.0 * x)
+
+
+def hyper_unpack(H, theta):
+    """Theta (flat) -> [(W_k, c_k)] for k = 1..K, widths H[0..K]."""
+    out, o = [], 0
+    for k in range(1, len(H)):
+        W = theta[o:o + H[k] * H[k - 1]].reshape(H[k], H[k - 1])
+        o += H[k] * H[k - 1]
+        c = theta[o:o + H[k]]
+        o += H[k]
+        out.append((W, c))
+    return out
+
+
+def hyper_forward(H, theta, mu):
+    """s = ReLU(NN(mu)) for mu [B][3]; returns (s [B][H_K], cache)."""
+    layers = hyper_unpack(H, _f(theta))
+    h = _f(mu)
+    pre = []
+    for k, (W, c) in enumerate(layers):
+        a = h @ W.T + c[None, :]
+        pre.append((h, a))
+        h = np.sin(a) if k < len(layers) - 1 else a
+    return _relu(h), (layers, pre)
+
+
+def sparse_reg_value(s, r, gamma):
+    """Mean over the sample rows of sum_l sum_i ReLU(-s_i^l + gamma s_{i+1}^l)."""
+    s = _f(s)
+    tot, o = 0.0, 0
+    for rl in r:
+        sl = s[:, o:o + rl]
+        t = -sl[:, :-1] + gamma * sl[:, 1:]
+        tot = tot + _relu(t).sum(axis=1)
+        o += rl
+    return np.mean(tot)
+
+
+def sparse_reg_grad(s, r, gamma):
+    """Per-row gradient of sum_l sum_i ReLU(-s_i + gamma s_{i+1}) w.r.t. s."""
+    s = _f(s)
+    g = np.zeros_like(s)
+    o = 0
+    for rl in r:
+        sl = s[:, o:o + rl]
+        act = (np.real(-sl[:, :-1] + gamma * sl[:, 1:]) > 0).astype(np.float64)
+        g[:, o:o + rl - 1] -= act
+        g[:, o + 1:o + rl] += gamma * act
+        o += rl
+    return g
+
+
+def hyper_backward(H, cache, s_bar):
+    """Theta gradient of sum_b <s_bar[b], s[b]> through the ReLU and the network."""
+    layers, pre = cache
+    K = len(layers)
+    h_in, a = pre[K - 1]
+    g = _f(s_bar) * (np.real(a) > 0)
+    grads = [None] * K
+    for k in range(K - 1, -1, -1):
+        h_in, a = pre[k]
+        W, _ = layers[k]
+        if k < K - 1:
+            g = g * np.cos(a)
+        grads[k] = (g.T @ h_in, g.sum(axis=0))
+        g = g @ W
+    return np.concatenate([np.concatenate([gW.ravel(), gc]) for gW, gc in grads])
+
+
+def meta_objective(net, H, theta, mus, pts, gamma, lam_sparse, cfg=None, with_grad=False):
+    """Eq. 3.4 with the bases fixed: mean over the samples mu_b of the
+    physics-informed loss of the LRNR at s = f_hyper(mu_b; Theta) on the
+    shared points, plus lam_sparse * R_sparse.  Returns (objective, grad)."""
+    s, cache = hyper_forward(H, theta, mus)
+    B = s.shape[0]
+    tot = 0.0
+    s_bar = np.zeros_like(s)
+    for b in range(B):
+        l4, gs, _ = lrnr_loss(net, net.split_s(s[b]), mus[b], pts, cfg, with_grad)
+        tot = tot + l4[0] / B
+        if with_grad:
+            s_bar[b] = gs / B
+    obj = tot + lam_sparse * sparse_reg_value(s, net.r, gamma)
+    if not with_grad:
+        return obj, None
+    s_bar = s_bar + lam_sparse * sparse_reg_grad(s, net.r, gamma) / B
+    return obj, hyper_backward(H, cache, s_bar)
 
 
 # --------------------------------------------------------------------------

@@ -458,3 +458,73 @@ def test_adam_closed_form_constant_gradient():
         # bias correction makes m_hat = g and v_hat = g^2 for a constant g
         expect = np.array([1.0, -2.0, 0.5]) - k * lr * g / (np.abs(g) + eps)
         np.testing.assert_allclose(s, expect, rtol=1e-12, atol=1e-15)
+
+
+# ------------------------------------------------------- meta-learning -----
+
+def _hyper_case(net, width=8, seed=21):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    H = [3, width, width, net.r_total]
+    theta = []
+    for k in range(1, len(H)):
+        theta.append(rng.standard_normal(H[k] * H[k - 1]) / math.sqrt(H[k - 1]))
+        theta.append(rng.uniform(0.2, 0.8, H[k]) if k == len(H) - 1 else rng.uniform(-0.5, 0.5, H[k]))
+    mus = np.stack([rng.uniform(1, 3, 3), rng.uniform(0, 2, 3), rng.uniform(0, 2, 3)], axis=1)
+    return H, np.concatenate(theta), mus
+
+
+def test_hyper_forward_backward_match_torch_autograd():
+    import torch
+    net, _, _ = tiny_case()
+    H, theta, mus = _hyper_case(net)
+    s, cache = orc.hyper_forward(H, theta, mus)
+    rng = np.random.default_rng(4)
+    s_bar = rng.standard_normal(s.shape)
+    g = orc.hyper_backward(H, cache, s_bar)
+    th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+    h = torch.tensor(mus, dtype=torch.float64)
+    o = 0
+    for k in range(1, len(H)):
+        W = th[o:o + H[k] * H[k - 1]].reshape(H[k], H[k - 1])
+        o += H[k] * H[k - 1]
+        c = th[o:o + H[k]]
+        o += H[k]
+        h = torch.nn.functional.linear(h, W, c)
+        if k < len(H) - 1:
+            h = torch.sin(h)
+    st = torch.relu(h)
+    np.testing.assert_allclose(s, st.detach().numpy(), rtol=1e-13, atol=1e-14)
+    (st * torch.tensor(s_bar)).sum().backward()
+    np.testing.assert_allclose(g, th.grad.numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_sparse_reg_zero_on_geometric_decay_and_hand_values():
+    # R_sparse vanishes when s_{i+1} < s_i / gamma (the decay it promotes)
+    r = [4, 3]
+    gamma = 2.0
+    s = np.array([[1.0, 0.4, 0.15, 0.05, 2.0, 0.9, 0.3]])
+    assert orc.sparse_reg_value(s, r, gamma) == 0.0
+    assert np.all(orc.sparse_reg_grad(s, r, gamma) == 0.0)
+    # flat coefficients: every term is (gamma - 1) s
+    s = np.array([[1.0, 1.0, 1.0, 1.0, 0.5, 0.5, 0.5]])
+    assert orc.sparse_reg_value(s, r, gamma) == pytest.approx(3 * 1.0 + 2 * 0.5)
+    np.testing.assert_allclose(orc.sparse_reg_grad(s, r, gamma)[0],
+                               [-1, 1, 1, 2, -1, 1, 2])
+    # the layers do not couple: the last entry of one layer and the first of
+    # the next form no term
+    s = np.array([[1.0, 0.1, 0.01, 0.001, 100.0, 1.0, 0.01]])
+    assert orc.sparse_reg_value(s, r, gamma) == 0.0
+
+
+def test_meta_objective_grad_complex_step():
+    net, pts, _ = tiny_case(n=15)
+    H, theta, mus = _hyper_case(net)
+    cfg = {"form": 0, "w_r": 1.0, "w_0": 1.0, "w_b": 1.0}
+    obj, g = orc.meta_objective(net, H, theta, mus, pts, 1.5, 0.3, cfg, with_grad=True)
+    c = _complex_step_grad(lambda z: orc.meta_objective(net, H, z, mus, pts, 1.5, 0.3, cfg)[0],
+                           theta)
+    np.testing.assert_allclose(g, c, rtol=1e-10, atol=1e-13)
+    # the objective is the mean of the per-sample losses plus the weighted term
+    s, _ = orc.hyper_forward(H, theta, mus)
+    per = [orc.lrnr_loss(net, net.split_s(s[b]), mus[b], pts, cfg)[0][0] for b in range(len(mus))]
+    assert obj == pytest.approx(np.mean(per) + 0.3 * orc.sparse_reg_value(s, net.r, 1.5), rel=1e-14)
