@@ -438,6 +438,66 @@ def run_reference(args, torch, api, wl, big):
     }
 
 
+def run_meta(args, torch, api, wl):
+    """Meta-learning of the coefficient map with fixed bases (Section 3.1,
+    eq. 3.1-3.4 without the basis updates): the small net, 64 parameter
+    samples sharing 16384 interior (+2048 IC, +2048 BC) points, hypernetwork
+    widths (3, 33, 33, 33), R_sparse with gamma = 1.5 and weight 1e-3, Adam
+    (lr 1e-3) on Theta for 200 steps.  Reported: ms per meta step (hypernetwork
+    forward, batched loss gradient, hypernetwork backward, Adam), its parts,
+    and the objective at the first and last step."""
+    w = wl.batched_case()
+    net = api.DeviceNet.from_net(w.net)
+    pts = api.DevicePoints.from_points(w.pts)
+    mu = torch.tensor(w.mu, device="cuda")
+    R = w.net.r_total
+    H = [3, R, R, R]
+    theta = torch.tensor(wl.hyper_init(H), device="cuda")
+    f = api.Hyper(H, theta)
+    m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+    cfg = api.LossCfg()
+    ws = api.Workspace()
+    gamma, lam = 1.5, 1e-3
+    hist = []
+
+    def step(k, record=False):
+        g, loss, r = api.meta_grad(f, net, mu, pts, cfg, gamma, lam, ws=ws)
+        api.adam_step(theta, m, v, g, k)
+        if record:
+            hist.append((loss, r))
+
+    step(1, True)
+    torch.cuda.synchronize()
+    n_steps = 200
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for k in range(2, n_steps + 1):
+        step(k, record=(k == n_steps))
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / (n_steps - 1)
+    s = api.hyper_forward(f, mu)
+    gs, _ = api.grad_s_batched(net, s, mu, pts, cfg, ws=ws)
+    ms_f = time_calls(torch, lambda: api.hyper_forward(f, mu), 20, 3)
+    ms_g = time_calls(torch, lambda: api.grad_s_batched(net, s, mu, pts, cfg, ws=ws), 20, 3)
+    ms_b = time_calls(torch, lambda: api.hyper_backward(f, net, mu, gs, gamma, lam), 20, 3)
+
+    def obj(i):
+        loss, r = hist[i]
+        return float(loss[:, 0].double().mean()) + lam * float(r[0])
+
+    n_r = pts.counts[0]
+    return {
+        "workload": "small net 64 wide x 4 hidden, rank 8; 64 mu samples sharing 16384 interior "
+                    "(+2048 IC, +2048 BC) points; hypernetwork (3, 33, 33, 33), sin, ReLU output; "
+                    "gamma 1.5, lambda_sparse 1e-3; Adam lr 1e-3, 200 steps",
+        "ms_per_meta_step": ms, "pts_per_s": 64 * n_r / (ms * 1e-3),
+        "hyper_forward_ms": ms_f, "batched_grad_ms": ms_g, "hyper_backward_ms": ms_b,
+        "objective_first": obj(0), "objective_last": obj(1),
+        "theta_params": int(theta.numel()),
+    }
+
+
 def cpu_reference_solver(wl):
     """The oracle's reference solver on the same 20 test parameters (numpy FFT
     Strang splitting, FP64), one pass."""
@@ -630,6 +690,7 @@ def main():
     ap.add_argument("--no-fidelity", action="store_true")
     ap.add_argument("--no-reference", action="store_true")
     ap.add_argument("--no-bias", action="store_true")
+    ap.add_argument("--no-meta", action="store_true")
     ap.add_argument("--serve-rates", type=lambda x: [float(v) for v in x.split(",")],
                     default=[50, 100, 200, 500, 1000, 2000])
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -697,6 +758,8 @@ def main():
                                  for big in (False, True)]
     if not args.no_reference:
         out["reference"] = [run_reference(args, torch, api, wl, big) for big in (False, True)]
+    if not args.no_meta:
+        out["meta"] = run_meta(args, torch, api, wl)
     if not args.no_diff:
         out["differentiation"] = run_differentiation(args, torch, api, wl)
     if not args.no_serve:

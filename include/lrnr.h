@@ -456,6 +456,48 @@ int32_t fastlrnr_bias_basis(const fastlrnr_handle* h, const lrnr_bias_basis* ful
                             float* B_hat, lrnr_bias_basis* reduced, void* stream);
 
 /*
+ * Meta-learning of the coefficient map (Section 3.1, eq. 3.1-3.4) with the
+ * bases U, V, b held fixed.  The hypernetwork s = f_hyper(mu; Theta) is a
+ * network of the form of eq. 2.1 with the activation sin on its hidden
+ * layers and a ReLU on its output (non-negative coefficients):
+ *  K     layers, 1..LRNR_MAX_LAYERS
+ *  H[k]  widths, H[0] = 3 (mu), H[K] = the net's r_total, each <= 256
+ *  theta [dev] per layer k = 1..K: W_k [H[k]][H[k-1]] row-major, then c_k [H[k]]
+ */
+typedef struct lrnr_hyper {
+  int32_t K;
+  int32_t H[LRNR_MAX_LAYERS + 1];
+  const float* theta;
+} lrnr_hyper;
+
+/* s [dev] [B][H[K]] out = f_hyper(mu[b]) for mu [dev] [B][3].  B = 0 is a no-op. */
+int32_t lrnr_hyper_forward(const lrnr_hyper* f, int32_t B, const float* mu, float* s,
+                           void* stream);
+
+/*
+ * Theta gradient of the meta objective (eq. 3.4 with fixed bases)
+ *   (1/B) sum_b [ L_b(s_b) + lambda_sparse R_sparse(s_b) ],  s_b = f_hyper(mu_b),
+ * given s_bar [dev] [B][r_total] = dL_b/ds_b (e.g. from lrnr_grad_s_batched at
+ * s = lrnr_hyper_forward(mu)).  R_sparse (eq. 3.3) = sum_l || ReLU(Gamma^l s^l) ||_1,
+ * Gamma^l [(r_l - 1) x r_l] with -1 on the diagonal and gamma above it; the
+ * net supplies the ranks r_l.
+ *  grad_theta [dev] out, the size of theta (overwritten, not accumulated)
+ *  r_sparse   [dev] [1] out, (1/B) sum_b R_sparse(s_b); may be NULL
+ *  ws         [dev] workspace of lrnr_hyper_workspace_size(f, B) bytes
+ *             (per-sample gradients), 256-B aligned
+ * B >= 1.  The per-sample gradients are summed over the samples in a fixed
+ * order (FP64): results are bitwise reproducible.  LRNR_EINVAL on shapes that
+ * do not match the net, LRNR_ENOMEM on a short workspace.
+ */
+int32_t lrnr_hyper_backward(const lrnr_hyper* f, const lrnr_net* net, int32_t B, const float* mu,
+                            const float* s_bar, float gamma, float lambda_sparse,
+                            float* grad_theta, float* r_sparse, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/* Workspace bytes of lrnr_hyper_backward for B samples (0 if f or B is invalid). */
+size_t lrnr_hyper_workspace_size(const lrnr_hyper* f, int32_t B);
+
+/*
  * Reference solution of the convection-diffusion-reaction problem of
  * Section 4, eq. 4.1 (u_t + mu_1 u_x - mu_2 u_xx - mu_3 u (1 - u) = 0 on
  * (0, 2 pi) periodic, u(x, 0) = sin x), for B parameter instances at once:

@@ -55,6 +55,14 @@ class LrnrBiasBasis(C.Structure):
     ]
 
 
+class LrnrHyper(C.Structure):
+    _fields_ = [
+        ("K", C.c_int32),
+        ("H", C.c_int32 * (MAX_LAYERS + 1)),
+        ("theta", C.c_void_p),
+    ]
+
+
 SEL_DEIM, SEL_QDEIM = 0, 1  # include/lrnr.h LRNR_SEL_*
 MODE_JETS, MODE_VALUE, MODE_LOSS, MODE_GRAD, MODE_VJP = 0, 1, 2, 3, 4
 
@@ -149,6 +157,10 @@ SIGNATURES = {
     "lrnr_bias_compose": (I32, [C.POINTER(LrnrBiasBasis), P, P, P]),
     "lrnr_bias_grad": (I32, [C.POINTER(LrnrBiasBasis), P, P, P]),
     "fastlrnr_bias_basis": (I32, [P, C.POINTER(LrnrBiasBasis), P, C.POINTER(LrnrBiasBasis), P]),
+    "lrnr_hyper_forward": (I32, [C.POINTER(LrnrHyper), I32, P, P, P]),
+    "lrnr_hyper_backward": (I32, [C.POINTER(LrnrHyper), NETP, I32, P, P, F32, F32, P, P, P, SZ,
+                                  P]),
+    "lrnr_hyper_workspace_size": (SZ, [C.POINTER(LrnrHyper), I32]),
     "lrnr_cdr_reference": (I32, [P, I32, I32, I32, I32, C.c_double, P, P, P]),
     "lrnr_l1_error": (I32, [P, P, I64, P, P]),
     "lrnr_status_string": (C.c_char_p, [I32]),

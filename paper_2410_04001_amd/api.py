@@ -391,6 +391,58 @@ def grad_s_factored(net, bb, s, s_b, mu, pts, cfg, ws=None):
     return gs, bias_grad(bb, gb), loss
 
 
+class Hyper:
+    """The hypernetwork f_hyper (lrnr_hyper): widths H[0..K] (H[0] = 3,
+    H[K] = r_total) and the packed parameters theta (device float32)."""
+
+    def __init__(self, H, theta):
+        self.H = [int(h) for h in H]
+        self.K = len(self.H) - 1
+        self.theta = theta
+        self._c = cl.LrnrHyper()
+        self._c.K = self.K
+        for k, h in enumerate(self.H):
+            self._c.H[k] = h
+        self._c.theta = theta.data_ptr()
+
+    @staticmethod
+    def n_params(H):
+        return sum(H[k] * H[k - 1] + H[k] for k in range(1, len(H)))
+
+    def c(self):
+        return C.byref(self._c)
+
+
+def hyper_forward(f, mu):
+    """s [B][r_total] = f_hyper(mu) for mu [B][3] (lrnr_hyper_forward)."""
+    s = torch.empty((mu.shape[0], f.H[-1]), dtype=torch.float32, device=mu.device)
+    cl.check(cl.lib().lrnr_hyper_forward(f.c(), mu.shape[0], _p(mu), _p(s), _stream()),
+             "lrnr_hyper_forward")
+    return s
+
+
+def hyper_backward(f, net, mu, s_bar, gamma, lambda_sparse, ws=None):
+    """(grad_theta, R_sparse) of the meta objective (lrnr_hyper_backward)."""
+    ws = ws or _ws(mu.device)
+    wp, wn = ws.ptr_size(cl.lib().lrnr_hyper_workspace_size(f.c(), mu.shape[0]))
+    g = torch.empty_like(f.theta)
+    r = torch.empty(1, dtype=torch.float32, device=mu.device)
+    cl.check(cl.lib().lrnr_hyper_backward(f.c(), net.c(), mu.shape[0], _p(mu), _p(s_bar),
+                                          float(gamma), float(lambda_sparse), _p(g), _p(r),
+                                          wp, wn, _stream()), "lrnr_hyper_backward")
+    return g, r
+
+
+def meta_grad(f, net, mu, pts, cfg, gamma, lambda_sparse, ws=None):
+    """One gradient of the meta objective with fixed bases: s = f_hyper(mu),
+    the batched loss gradient at s, then the hypernetwork backward.  Returns
+    (grad_theta, per-sample losses [B][4], R_sparse) as device tensors."""
+    s = hyper_forward(f, mu)
+    gs, loss = grad_s_batched(net, s, mu, pts, cfg, ws=ws)
+    g, r = hyper_backward(f, net, mu, gs, gamma, lambda_sparse, ws=ws)
+    return g, loss, r
+
+
 def cdr_reference(mu, n_x, n_t, n_out, t_end=1.0):
     """Reference solution of eq. 4.1 for mu [B][3] (float64 device tensor) by
     lrnr_cdr_reference: returns (u [B][n_out][n_x] float64, status [B] int32),

@@ -1,0 +1,244 @@
+// Meta-learning of the coefficient map (Section 3.1): the hypernetwork
+// s = f_hyper(mu; Theta) (eq. 3.1), a network of the form of eq. 2.1 with the
+// activation sin and a ReLU on its output, and the Theta gradient of the meta
+// objective of eq. 3.4 with the bases held fixed:
+//   (1/B) sum_b [ L(s_b; mu_b) + lambda R_sparse(s_b) ],
+// where dL/ds_b comes from the batched loss gradient and R_sparse (eq. 3.3)
+// is sum_l || ReLU(Gamma^l s^l) ||_1 with Gamma^l banded (-1 on the diagonal,
+// gamma above it).
+//
+// The network is small (widths <= 256): forward and per-sample backward run
+// one workgroup per sample; the per-sample gradients land in rows of a caller
+// workspace and are summed over the samples in a fixed order (FP64), which
+// keeps the result deterministic without atomics.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "lrnr_internal.h"
+
+namespace lrnr {
+namespace {
+
+constexpr int kHyperThreads = 256;
+constexpr int kHyperMaxW = 256;
+
+struct KHyper {
+  int K;
+  int H[LRNR_MAX_LAYERS + 1];
+  int64_t offW[LRNR_MAX_LAYERS + 1];
+  int64_t offC[LRNR_MAX_LAYERS + 1];
+  const float* theta;
+  // coefficient layout of the LRNR (for R_sparse): layer of each entry
+  int L;
+  int offS[LRNR_MAX_LAYERS + 2];
+};
+
+__global__ void __launch_bounds__(kHyperThreads) hyper_forward_kernel(KHyper f, const float* mu,
+                                                                      float* s) {
+  __shared__ float h[2][kHyperMaxW];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  if (tid < 3) h[0][tid] = mu[3 * b + tid];
+  __syncthreads();
+  int cur = 0;
+  for (int k = 1; k <= f.K; ++k) {
+    const int Hp = f.H[k - 1], Hk = f.H[k];
+    const float* W = f.theta + f.offW[k];
+    const float* c = f.theta + f.offC[k];
+    for (int j = tid; j < Hk; j += kHyperThreads) {
+      float a = c[j];
+      for (int i = 0; i < Hp; ++i) a = fmaf(W[(int64_t)j * Hp + i], h[cur][i], a);
+      h[cur ^ 1][j] = (k < f.K) ? sinf(a) : fmaxf(a, 0.f);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  const int R = f.H[f.K];
+  for (int j = tid; j < R; j += kHyperThreads) s[(int64_t)b * R + j] = h[cur][j];
+}
+
+// One workgroup per sample b: forward, then the gradient of
+// <(s_bar_b + lambda dR_b/ds) / B, s_b> with respect to Theta into row b of the
+// workspace, and R_sparse(s_b) into its last entry.
+__global__ void __launch_bounds__(kHyperThreads) hyper_sample_grad_kernel(
+    KHyper f, int B, const float* mu, const float* s_bar, float gamma, float lam, float* ws,
+    int64_t n_theta) {
+  __shared__ float hin[LRNR_MAX_LAYERS + 1][kHyperMaxW];   // input of layer k at [k]
+  __shared__ float pre[LRNR_MAX_LAYERS + 1][kHyperMaxW];   // pre-activation of layer k
+  __shared__ float g[2][kHyperMaxW];
+  __shared__ float red[kHyperThreads];
+  const int b = blockIdx.x, tid = threadIdx.x, K = f.K, R = f.H[K];
+  const float invB = 1.0f / (float)B;
+  float* grad = ws + (int64_t)b * (n_theta + 1);
+  if (tid < 3) hin[1][tid] = mu[3 * b + tid];
+  __syncthreads();
+  for (int k = 1; k <= K; ++k) {
+    const int Hp = f.H[k - 1], Hk = f.H[k];
+    const float* W = f.theta + f.offW[k];
+    const float* c = f.theta + f.offC[k];
+    for (int j = tid; j < Hk; j += kHyperThreads) {
+      float a = c[j];
+      for (int i = 0; i < Hp; ++i) a = fmaf(W[(int64_t)j * Hp + i], hin[k][i], a);
+      pre[k][j] = a;
+      if (k < K) hin[k + 1][j] = sinf(a);
+    }
+    __syncthreads();
+  }
+  // output gradient: ReLU, plus the R_sparse term on s = ReLU(pre_K)
+  float rsum = 0.f;
+  for (int m = tid; m < R; m += kHyperThreads) {
+    int l = 1;
+    while (m >= f.offS[l + 1]) ++l;
+    const int i = m - f.offS[l], rl = f.offS[l + 1] - f.offS[l];
+    const float sm = fmaxf(pre[K][m], 0.f);
+    float dr = 0.f;
+    if (i + 1 < rl) {
+      const float t = -sm + gamma * fmaxf(pre[K][m + 1], 0.f);
+      if (t > 0.f) {
+        dr -= 1.f;
+        rsum += t;
+      }
+    }
+    if (i > 0) {
+      const float t = -fmaxf(pre[K][m - 1], 0.f) + gamma * sm;
+      if (t > 0.f) dr += gamma;
+    }
+    const float gs = (s_bar[(int64_t)b * R + m] + lam * dr) * invB;
+    g[K & 1][m] = (pre[K][m] > 0.f) ? gs : 0.f;
+  }
+  red[tid] = rsum;
+  __syncthreads();
+  for (int k = K; k >= 1; --k) {
+    const int Hp = f.H[k - 1], Hk = f.H[k];
+    const float* gk = g[k & 1];
+    const int64_t nW = (int64_t)Hk * Hp;
+    float* gW = grad + f.offW[k];
+    for (int64_t e = tid; e < nW; e += kHyperThreads) {
+      const int j = (int)(e / Hp), i = (int)(e - (int64_t)j * Hp);
+      gW[e] = gk[j] * hin[k][i];
+    }
+    float* gc = grad + f.offC[k];
+    for (int j = tid; j < Hk; j += kHyperThreads) gc[j] = gk[j];
+    if (k > 1) {
+      const float* W = f.theta + f.offW[k];
+      for (int i = tid; i < Hp; i += kHyperThreads) {
+        float acc = 0.f;
+        for (int j = 0; j < Hk; ++j) acc = fmaf(W[(int64_t)j * Hp + i], gk[j], acc);
+        g[(k - 1) & 1][i] = acc * cosf(pre[k - 1][i]);
+      }
+    }
+    __syncthreads();
+  }
+  for (int w = kHyperThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) grad[n_theta] = red[0];
+}
+
+// grad_theta[e] = sum_b ws[b][e] (b ascending, FP64); r_sparse = mean_b ws[b][n_theta]
+__global__ void __launch_bounds__(kHyperThreads) hyper_sum_kernel(const float* ws, int B,
+                                                                  int64_t n_theta, float* grad,
+                                                                  float* r_sparse) {
+  const int64_t e = (int64_t)blockIdx.x * kHyperThreads + threadIdx.x;
+  const int64_t stride = n_theta + 1;
+  if (e < n_theta) {
+    double acc = 0.0;
+    for (int b = 0; b < B; ++b) acc += (double)ws[(int64_t)b * stride + e];
+    grad[e] = (float)acc;
+  } else if (e == n_theta && r_sparse) {
+    double acc = 0.0;
+    for (int b = 0; b < B; ++b) acc += (double)ws[(int64_t)b * stride + n_theta];
+    r_sparse[0] = (float)(acc / B);
+  }
+}
+
+int32_t make_khyper(const lrnr_hyper* f, KHyper* k) {
+  if (!f) return fail(LRNR_EINVAL, "NULL hypernetwork");
+  if (f->K < 1 || f->K > LRNR_MAX_LAYERS) return fail(LRNR_EINVAL, "hypernetwork K=%d", f->K);
+  if (f->H[0] != 3) return fail(LRNR_EINVAL, "hypernetwork H[0]=%d, expected 3 (mu)", f->H[0]);
+  if (!f->theta) return fail(LRNR_EINVAL, "NULL theta");
+  *k = KHyper{};
+  k->K = f->K;
+  k->H[0] = 3;
+  int64_t o = 0;
+  for (int l = 1; l <= f->K; ++l) {
+    const int h = f->H[l];
+    if (h < 1 || h > kHyperMaxW) return fail(LRNR_EINVAL, "hypernetwork H[%d]=%d", l, h);
+    k->H[l] = h;
+    k->offW[l] = o;
+    o += (int64_t)h * f->H[l - 1];
+    k->offC[l] = o;
+    o += h;
+  }
+  k->theta = f->theta;
+  return LRNR_OK;
+}
+
+int64_t hyper_params(const KHyper& k) { return k.offC[k.K] + k.H[k.K]; }
+
+}  // namespace
+}  // namespace lrnr
+
+using namespace lrnr;
+
+extern "C" {
+
+int32_t lrnr_hyper_forward(const lrnr_hyper* f, int32_t B, const float* mu, float* s,
+                           void* stream) {
+  KHyper k;
+  int32_t rc = make_khyper(f, &k);
+  if (rc != LRNR_OK) return rc;
+  if (B < 0) return fail(LRNR_EINVAL, "B=%d", B);
+  if (B == 0) return LRNR_OK;
+  if (!mu || !s) return fail(LRNR_EINVAL, "NULL mu or s");
+  hipLaunchKernelGGL(hyper_forward_kernel, dim3(B), dim3(kHyperThreads), 0,
+                     static_cast<hipStream_t>(stream), k, mu, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "hypernetwork forward launch");
+  return LRNR_OK;
+}
+
+size_t lrnr_hyper_workspace_size(const lrnr_hyper* f, int32_t B) {
+  KHyper k;
+  if (make_khyper(f, &k) != LRNR_OK || B < 1) return 0;
+  return align256((size_t)B * (size_t)(hyper_params(k) + 1) * sizeof(float));
+}
+
+int32_t lrnr_hyper_backward(const lrnr_hyper* f, const lrnr_net* net, int32_t B, const float* mu,
+                            const float* s_bar, float gamma, float lambda_sparse,
+                            float* grad_theta, float* r_sparse, void* ws, size_t ws_bytes,
+                            void* stream) {
+  KHyper k;
+  int32_t rc = make_khyper(f, &k);
+  if (rc != LRNR_OK) return rc;
+  KNet kn;
+  int RP, Wp;
+  rc = make_knet(net, &kn, &RP, &Wp);
+  if (rc != LRNR_OK) return rc;
+  if (k.H[k.K] != kn.r_total)
+    return fail(LRNR_EINVAL, "hypernetwork output %d, net r_total %d", k.H[k.K], kn.r_total);
+  if (B < 1) return fail(LRNR_EINVAL, "B=%d (at least one sample)", B);
+  if (!mu || !s_bar || !grad_theta) return fail(LRNR_EINVAL, "NULL mu, s_bar or grad_theta");
+  const size_t need = lrnr_hyper_workspace_size(f, B);
+  if (!ws || ws_bytes < need)
+    return fail(LRNR_ENOMEM, "workspace %zu bytes, need %zu", ws_bytes, need);
+  k.L = kn.L;
+  for (int l = 1; l <= kn.L; ++l) k.offS[l] = kn.offS[l];
+  k.offS[kn.L + 1] = kn.r_total;
+  const int64_t n_theta = hyper_params(k);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float* w = static_cast<float*>(ws);
+  hipLaunchKernelGGL(hyper_sample_grad_kernel, dim3(B), dim3(kHyperThreads), 0, st, k, B, mu,
+                     s_bar, gamma, lambda_sparse, w, n_theta);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "hypernetwork backward launch");
+  const int64_t nb = (n_theta + 1 + kHyperThreads - 1) / kHyperThreads;
+  hipLaunchKernelGGL(hyper_sum_kernel, dim3((unsigned)nb), dim3(kHyperThreads), 0, st, w, B,
+                     n_theta, grad_theta, r_sparse);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "hypernetwork sum launch");
+  return LRNR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+"""GPU parity of the meta-learning kernels (lrnr_hyper_forward,
+lrnr_hyper_backward, and the meta gradient built from them and the batched
+loss gradient) against the FP64 oracle.  Bar: 1e-4 relative in the 2-norm
+and the max-norm (the bar of the loss and s-gradients; the Theta gradient is
+a linear image of the s-gradients)."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import lrnr_oracle as orc
+
+from _util import assert_close, log
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "the gpu tests need the MI355X"
+    from paper_2410_04001_amd import _clib
+    _clib.lib()
+
+
+def api():
+    from paper_2410_04001_amd import api as a
+    return a
+
+
+def setup(make, B, seed=3):
+    a = api()
+    w = make()
+    R = w.net.r_total
+    H = [3, R, R, R]
+    theta = wl.hyper_init(H)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mus = wl.make_mu(rng, B)
+    f = a.Hyper(H, torch.tensor(theta, device="cuda"))
+    return a, w, H, theta, mus, f
+
+
+NETS = [("small", lambda: wl.small_lrnr(0, 2048)), ("wide", lambda: wl.big_lrnr(1, 2048))]
+
+
+@pytest.mark.parametrize("name,make", NETS, ids=[n for n, _ in NETS])
+def test_hyper_forward_backward_match_oracle(name, make):
+    a, w, H, theta, mus, f = setup(make, 37)
+    log(f"[case] hypernetwork {name}: H={H} B=37")
+    mu_d = torch.tensor(mus, device="cuda")
+    s = a.hyper_forward(f, mu_d)
+    rs, cache = orc.hyper_forward(H, theta, mus.astype(np.float64))
+    assert_close(s.cpu().numpy(), rs, TOL, f"{name} s")
+    rng = np.random.Generator(np.random.PCG64(8))
+    s_bar = rng.standard_normal(rs.shape).astype(np.float32)
+    net = a.DeviceNet.from_net(w.net)
+    g, r = a.hyper_backward(f, net, mu_d, torch.tensor(s_bar, device="cuda"), 1.5, 0.3)
+    g2, _ = a.hyper_backward(f, net, mu_d, torch.tensor(s_bar, device="cuda"), 1.5, 0.3)
+    torch.cuda.synchronize()
+    B = len(mus)
+    sb_ref = s_bar / B + 0.3 * orc.sparse_reg_grad(rs, w.net.r, 1.5) / B
+    assert_close(g.cpu().numpy(), orc.hyper_backward(H, cache, sb_ref), TOL, f"{name} grad theta")
+    r_ref = orc.sparse_reg_value(rs, w.net.r, 1.5)
+    assert abs(float(r[0]) - r_ref) <= TOL * max(1.0, abs(r_ref)), (float(r[0]), r_ref)
+    assert torch.equal(g, g2)                      # fixed order: bitwise repeatable
+
+
+def test_meta_gradient_matches_oracle():
+    a, w, H, theta, mus, f = setup(lambda: wl.small_lrnr(0, 2048), 4)
+    log("[case] meta gradient, small net, B=4, N=2048")
+    net = a.DeviceNet.from_net(w.net)
+    pts = a.DevicePoints.from_points(w.pts)
+    g, loss, r = a.meta_grad(f, net, torch.tensor(mus, device="cuda"), pts, a.LossCfg(), 1.5, 0.3)
+    torch.cuda.synchronize()
+    obj, rg = orc.meta_objective(w.net, H, theta.astype(np.float64), mus.astype(np.float64),
+                                 w.pts, 1.5, 0.3, {}, with_grad=True)
+    got = float(loss[:, 0].double().mean()) + 0.3 * float(r[0])
+    assert abs(got - obj) <= TOL * abs(obj), (got, obj)
+    assert_close(g.cpu().numpy(), rg, TOL, "meta grad theta")
+
+
+def test_hyper_argument_checks():
+    a, w, H, theta, mus, f = setup(lambda: wl.small_lrnr(0, 256), 2)
+    from paper_2410_04001_amd import _clib as cl
+    net = a.DeviceNet.from_net(w.net)
+    mu_d = torch.tensor(mus, device="cuda")
+    bad = a.Hyper([2] + H[1:], f.theta)            # H[0] must be 3
+    with pytest.raises(RuntimeError):
+        a.hyper_forward(bad, mu_d)
+    short = a.Hyper(H[:-1] + [H[-1] - 1], f.theta)  # output is not r_total
+    with pytest.raises(RuntimeError):
+        a.hyper_backward(short, net, mu_d, torch.zeros((2, H[-1] - 1), device="cuda"), 1.5, 0.1)
+    g = torch.empty_like(f.theta)
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    rc = cl.lib().lrnr_hyper_backward(f.c(), net.c(), 0, mu_d.data_ptr(), mu_d.data_ptr(),
+                                      1.5, 0.1, g.data_ptr(), None, ws.data_ptr(), ws.numel(), None)
+    assert rc == cl.EINVAL                          # no samples
+    s_bar = torch.zeros((2, H[-1]), device="cuda")
+    rc = cl.lib().lrnr_hyper_backward(f.c(), net.c(), 2, mu_d.data_ptr(), s_bar.data_ptr(),
+                                      1.5, 0.1, g.data_ptr(), None, ws.data_ptr(), 64, None)
+    assert rc == cl.ENOMEM                          # workspace too small
+    assert cl.lib().lrnr_hyper_workspace_size(f.c(), 0) == 0
+    empty = a.hyper_forward(f, torch.zeros((0, 3), device="cuda"))
+    assert empty.shape == (0, H[-1])

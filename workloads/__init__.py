@@ -235,6 +235,19 @@ def cdr_test_cases(seed: int = 5, n1: int = 10, n2: int = 10) -> np.ndarray:
     return np.concatenate([d1, d2])
 
 
+def hyper_init(H: list, seed: int = 7) -> np.ndarray:
+    """Parameters of a hypernetwork with widths H (packed per layer as W_k
+    [H_k][H_{k-1}] row-major, then c_k): W ~ N(0, 1/H_{k-1}); hidden biases
+    U(-0.5, 0.5); output biases U(0.5, 1.5), the range of the nets' s."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(1, len(H)):
+        out.append(rng.standard_normal(H[k] * H[k - 1]) / math.sqrt(H[k - 1]))
+        lo, hi = (0.5, 1.5) if k == len(H) - 1 else (-0.5, 0.5)
+        out.append(rng.uniform(lo, hi, H[k]))
+    return np.concatenate(out).astype(np.float32)
+
+
 def serving_stream(seed: int = 4, n_req: int = 2000, rate: float = 500.0):
     """Poisson stream of new-mu requests: arrival times (s), mu, point counts
     log-uniform in [1024, 65536], reduced widths drawn from {16, 32, 48}, and a
