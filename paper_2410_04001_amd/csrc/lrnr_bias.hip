@@ -44,8 +44,20 @@ __global__ void __launch_bounds__(kBiasThreads) bias_grad_kernel(KBias k, const 
   const float* B = k.B + k.offB[l];
   const float* g = gb + k.offb[l];
   for (int j = threadIdx.x; j < q; j += kBiasThreads) {
+    // loads issued eight rows at a time, added in row order
     double acc = 0.0;
-    for (int i = 0; i < M; ++i) acc += (double)B[(int64_t)i * q + j] * (double)g[i];
+    int i = 0;
+    for (; i + 8 <= M; i += 8) {
+      float bv[8], gv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        bv[u] = B[(int64_t)(i + u) * q + j];
+        gv[u] = g[i + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += (double)bv[u] * (double)gv[u];
+    }
+    for (; i < M; ++i) acc += (double)B[(int64_t)i * q + j] * (double)g[i];
     gsb[k.offS[l] + j] = (float)acc;
   }
 }

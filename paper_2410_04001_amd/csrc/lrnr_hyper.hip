@@ -142,15 +142,22 @@ __global__ void __launch_bounds__(kHyperThreads) hyper_sum_kernel(const float* w
                                                                   float* r_sparse) {
   const int64_t e = (int64_t)blockIdx.x * kHyperThreads + threadIdx.x;
   const int64_t stride = n_theta + 1;
-  if (e < n_theta) {
-    double acc = 0.0;
-    for (int b = 0; b < B; ++b) acc += (double)ws[(int64_t)b * stride + e];
-    grad[e] = (float)acc;
-  } else if (e == n_theta && r_sparse) {
-    double acc = 0.0;
-    for (int b = 0; b < B; ++b) acc += (double)ws[(int64_t)b * stride + n_theta];
-    r_sparse[0] = (float)(acc / B);
+  if (e > n_theta || (e == n_theta && !r_sparse)) return;
+  // loads issued eight at a time, added in sample order
+  double acc = 0.0;
+  int b = 0;
+  for (; b + 8 <= B; b += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = ws[(int64_t)(b + u) * stride + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += (double)v[u];
   }
+  for (; b < B; ++b) acc += (double)ws[(int64_t)b * stride + e];
+  if (e < n_theta)
+    grad[e] = (float)acc;
+  else
+    r_sparse[0] = (float)(acc / B);
 }
 
 int32_t make_khyper(const lrnr_hyper* f, KHyper* k) {
