@@ -59,7 +59,8 @@ def to_dev(w):
 
 CASES = [("small", lambda: wl.fast_case(2, n=8192), 8, None),
          ("small_zero_layer", lambda: wl.fast_case(2, n=4096), 6, 2),
-         ("wide", lambda: wl.big_lrnr(1, 8192), 16, None)]
+         ("wide", lambda: wl.big_lrnr(1, 8192), 16, None),
+         ("wide_q32", lambda: wl.big_lrnr(1, 2048), 32, None)]
 
 
 @pytest.mark.parametrize("name,make,q,zero", CASES, ids=[c[0] for c in CASES])

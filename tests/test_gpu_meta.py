@@ -103,3 +103,26 @@ def test_hyper_argument_checks():
     assert cl.lib().lrnr_hyper_workspace_size(f.c(), 0) == 0
     empty = a.hyper_forward(f, torch.zeros((0, 3), device="cuda"))
     assert empty.shape == (0, H[-1])
+
+
+@pytest.mark.parametrize("H_mid", [[], [256], [256, 256, 64]], ids=["K1", "wide256", "K4"])
+def test_hyper_depths_and_maximum_width(H_mid):
+    # one layer (linear + ReLU), the maximum width 256, and a deeper map
+    a = api()
+    w = wl.big_lrnr(1, 256)
+    R = w.net.r_total
+    H = [3] + H_mid + [R]
+    theta = wl.hyper_init(H, seed=11)
+    rng = np.random.Generator(np.random.PCG64(12))
+    mus = wl.make_mu(rng, 9)
+    log(f"[case] hypernetwork H={H} B=9")
+    f = a.Hyper(H, torch.tensor(theta, device="cuda"))
+    mu_d = torch.tensor(mus, device="cuda")
+    s = a.hyper_forward(f, mu_d)
+    rs, cache = orc.hyper_forward(H, theta, mus.astype(np.float64))
+    assert_close(s.cpu().numpy(), rs, TOL, f"H={H} s")
+    s_bar = rng.standard_normal(rs.shape).astype(np.float32)
+    net = a.DeviceNet.from_net(w.net)
+    g, r = a.hyper_backward(f, net, mu_d, torch.tensor(s_bar, device="cuda"), 2.0, 0.5)
+    sb_ref = s_bar / 9 + 0.5 * orc.sparse_reg_grad(rs, w.net.r, 2.0) / 9
+    assert_close(g.cpu().numpy(), orc.hyper_backward(H, cache, sb_ref), TOL, f"H={H} grad theta")
