@@ -9,7 +9,9 @@
 // throughout.
 //
 // Device layout: one workgroup per parameter instance, the grid of n_x values
-// in LDS as complex doubles.  The transform pair is a radix-2 decimation-in-
+// in LDS as complex doubles.  Grids of 4^m points take the radix-4 kernel
+// further down (half the passes); the others this one.  The transform pair is
+// a radix-2 decimation-in-
 // frequency forward FFT (natural order in, bit-reversed out) followed by a
 // decimation-in-time inverse FFT (bit-reversed in, natural out), so no
 // permutation pass is needed: the Fourier propagator is stored in bit-
@@ -177,6 +179,138 @@ __global__ void __launch_bounds__(256) cdr_strang_kernel(CdrArgs a) {
   if (tid == 0) a.status[inst] = 0;
 }
 
+__device__ inline double2 mul_mi(double2 a) { return make_double2(a.y, -a.x); }   // a * (-i)
+__device__ inline double2 mul_pi(double2 a) { return make_double2(-a.y, a.x); }   // a * (+i)
+
+// Radix-4 variant for n_x = 4^m (m >= 2): decimation in frequency with
+// radix-4 butterflies leaves the spectrum in base-4 digit-reversed order, the
+// propagator is stored in that order, and radix-4 decimation in time returns
+// to natural order.  One butterfly (four grid points) per thread and stage,
+// n_x/4 threads (one wave at n_x = 256): half the passes of the radix-2
+// kernel, 2m - 1 barriers per step.  The same fusions: the first reaction
+// half-step inside the outermost forward stage, the propagator between the
+// span-4 stages, the second half-step and the output inside the outermost
+// inverse stage (thread t owns points t + r n_x/4 there and 4t..4t+3 in the
+// span-4 stages).
+__global__ void __launch_bounds__(256) cdr_strang4_kernel(CdrArgs a) {
+  extern __shared__ double2 lds[];
+  const int N = a.n_x, Qn = N >> 2, m = a.log2n >> 1, tid = threadIdx.x;
+  double2* X = lds;            // [N]
+  double2* tw = lds + N;       // [N] exp(-2 pi i k / N)
+  double2* Pd = lds + 2 * N;   // [N] propagator / N at digit-reversed positions
+
+  const int inst = blockIdx.x;
+  const double beta = a.mu[3 * inst], nu = a.mu[3 * inst + 1], rho = a.mu[3 * inst + 2];
+  const double e = exp(rho * 0.5 * a.dt), em1 = expm1(rho * 0.5 * a.dt);
+  double* out = a.u + (int64_t)inst * a.n_out * N;
+  const int T = blockDim.x;
+
+  for (int k = tid; k < N; k += T) {
+    double sv, cv;
+    sincos((2.0 * M_PI) * k / N, &sv, &cv);
+    tw[k] = make_double2(cv, -sv);
+    int r = 0, i = k;
+    for (int d = 0; d < m; ++d) {
+      r = (r << 2) | (i & 3);
+      i >>= 2;
+    }
+    const double kk = (r < (N >> 1)) ? (double)r : (double)(r - N);   // wavenumber at k
+    sincos(beta * kk * a.dt, &sv, &cv);
+    const double g = exp(-nu * kk * kk * a.dt) / N;
+    Pd[k] = make_double2(g * cv, -g * sv);
+  }
+
+  double u[4];   // u at tid + r N/4
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    u[r] = sin((2.0 * M_PI) * (tid + r * Qn) / N);
+    out[tid + r * Qn] = u[r];
+  }
+  __syncthreads();
+
+  for (int n = 1; n <= a.n_t; ++n) {
+    bool bad = false;
+    {   // reaction half-step, forward stage of span N (p = tid, twiddle step 1)
+      double v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = react(u[r], e, em1, bad);
+      const double t0 = v[0] + v[2], t1 = v[0] - v[2], t2 = v[1] + v[3], t3 = v[1] - v[3];
+      // (t1 + t3*(-i)), (t1 - t3*(-i)) with t1, t3 real
+      X[tid] = make_double2(t0 + t2, 0.0);
+      X[tid + Qn] = cmul(make_double2(t1, -t3), tw[tid]);
+      X[tid + 2 * Qn] = make_double2((t0 - t2) * tw[2 * tid].x, (t0 - t2) * tw[2 * tid].y);
+      X[tid + 3 * Qn] = cmul(make_double2(t1, t3), tw[3 * tid]);
+    }
+    __syncthreads();
+    for (int s = m - 1; s >= 2; --s) {   // forward stages of span 4^s
+      const int q = 1 << (2 * (s - 1)), sh = 2 * (m - s);
+      const int p = tid & (q - 1), i0 = ((tid >> (2 * (s - 1))) << (2 * s)) + p;
+      const double2 x0 = X[i0], x1 = X[i0 + q], x2 = X[i0 + 2 * q], x3 = X[i0 + 3 * q];
+      const double2 t0 = cadd(x0, x2), t1 = csub(x0, x2), t2 = cadd(x1, x3),
+                    t3 = mul_mi(csub(x1, x3));
+      X[i0] = cadd(t0, t2);
+      X[i0 + q] = cmul(cadd(t1, t3), tw[p << sh]);
+      X[i0 + 2 * q] = cmul(csub(t0, t2), tw[(2 * p) << sh]);
+      X[i0 + 3 * q] = cmul(csub(t1, t3), tw[(3 * p) << sh]);
+      __syncthreads();
+    }
+    {   // span 4 forward, propagator, span 4 inverse (all twiddles 1)
+      const int i0 = 4 * tid;
+      const double2 x0 = X[i0], x1 = X[i0 + 1], x2 = X[i0 + 2], x3 = X[i0 + 3];
+      const double2 t0 = cadd(x0, x2), t1 = csub(x0, x2), t2 = cadd(x1, x3),
+                    t3 = mul_mi(csub(x1, x3));
+      const double2 a0 = cmul(cadd(t0, t2), Pd[i0]), a1 = cmul(cadd(t1, t3), Pd[i0 + 1]),
+                    a2 = cmul(csub(t0, t2), Pd[i0 + 2]), a3 = cmul(csub(t1, t3), Pd[i0 + 3]);
+      const double2 b0 = cadd(a0, a2), b1 = csub(a0, a2), b2 = cadd(a1, a3),
+                    b3 = mul_pi(csub(a1, a3));
+      X[i0] = cadd(b0, b2);
+      X[i0 + 1] = cadd(b1, b3);
+      X[i0 + 2] = csub(b0, b2);
+      X[i0 + 3] = csub(b1, b3);
+    }
+    __syncthreads();
+    for (int s = 2; s < m; ++s) {   // inverse stages of span 4^s
+      const int q = 1 << (2 * (s - 1)), sh = 2 * (m - s);
+      const int p = tid & (q - 1), i0 = ((tid >> (2 * (s - 1))) << (2 * s)) + p;
+      const double2 a0 = X[i0], a1 = cmul_conj(X[i0 + q], tw[p << sh]),
+                    a2 = cmul_conj(X[i0 + 2 * q], tw[(2 * p) << sh]),
+                    a3 = cmul_conj(X[i0 + 3 * q], tw[(3 * p) << sh]);
+      const double2 b0 = cadd(a0, a2), b1 = csub(a0, a2), b2 = cadd(a1, a3),
+                    b3 = mul_pi(csub(a1, a3));
+      X[i0] = cadd(b0, b2);
+      X[i0 + q] = cadd(b1, b3);
+      X[i0 + 2 * q] = csub(b0, b2);
+      X[i0 + 3 * q] = csub(b1, b3);
+      __syncthreads();
+    }
+    {   // inverse stage of span N (real parts only), second half-step
+      const double2 a0 = X[tid], a1 = cmul_conj(X[tid + Qn], tw[tid]),
+                    a2 = cmul_conj(X[tid + 2 * Qn], tw[2 * tid]),
+                    a3 = cmul_conj(X[tid + 3 * Qn], tw[3 * tid]);
+      const double2 b0 = cadd(a0, a2), b1 = csub(a0, a2), b2 = cadd(a1, a3),
+                    b3 = mul_pi(csub(a1, a3));
+      u[0] = react(b0.x + b2.x, e, em1, bad);
+      u[1] = react(b1.x + b3.x, e, em1, bad);
+      u[2] = react(b0.x - b2.x, e, em1, bad);
+      u[3] = react(b1.x - b3.x, e, em1, bad);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bad |= !(fabs(u[r]) <= kUMax);
+    }
+    if (__syncthreads_or(bad)) {
+      if (tid == 0) a.status[inst] = n;
+      for (int k = (n + a.every - 1) / a.every; k < a.n_out; ++k)
+        for (int j = tid; j < N; j += T) out[(int64_t)k * N + j] = __longlong_as_double(0x7ff8000000000000LL);
+      return;
+    }
+    if (n % a.every == 0) {
+      double* o = out + (int64_t)(n / a.every) * N;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) o[tid + r * Qn] = u[r];
+    }
+  }
+  if (tid == 0) a.status[inst] = 0;
+}
+
 // sum |pred - ref| and sum |ref| in FP64, one workgroup, fixed order: thread t
 // takes i = t, t + 1024, ... ascending, then a fixed tree over the threads.
 __global__ void __launch_bounds__(kL1Threads) l1_error_kernel(const float* pred, const double* ref,
@@ -233,13 +367,18 @@ int32_t lrnr_cdr_reference(const double* mu, int32_t B, int32_t n_x, int32_t n_t
   a.dt = t_end / n_t;
   a.u = u;
   a.status = status;
-  const int T = n_x / 2 < 256 ? n_x / 2 : 256;
-  const size_t lds = (size_t)(n_x + n_x / 2 + n_x) * sizeof(double2);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (n_x / 2 <= 256)
-    hipLaunchKernelGGL(cdr_strang_kernel<1>, dim3(B), dim3(T), lds, st, a);
-  else
-    hipLaunchKernelGGL(cdr_strang_kernel<2>, dim3(B), dim3(T), lds, st, a);
+  if ((a.log2n & 1) == 0) {   // n_x = 4^m, m >= 2: radix-4 pair, n_x / 4 threads
+    const size_t lds = (size_t)3 * n_x * sizeof(double2);
+    hipLaunchKernelGGL(cdr_strang4_kernel, dim3(B), dim3(n_x / 4), lds, st, a);
+  } else {
+    const int T = n_x / 2 < 256 ? n_x / 2 : 256;
+    const size_t lds = (size_t)(n_x + n_x / 2 + n_x) * sizeof(double2);
+    if (n_x / 2 <= 256)
+      hipLaunchKernelGGL(cdr_strang_kernel<1>, dim3(B), dim3(T), lds, st, a);
+    else
+      hipLaunchKernelGGL(cdr_strang_kernel<2>, dim3(B), dim3(T), lds, st, a);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "cdr solver launch");
   return LRNR_OK;

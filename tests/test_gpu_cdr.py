@@ -60,8 +60,11 @@ def run(mus, n_x, n_t, n_out, t_end=1.0):
     return u.cpu().numpy(), st.cpu().numpy()
 
 
-@pytest.mark.parametrize("n_x,n_t,n_out", [(8, 20, 5), (64, 200, 11), (256, 500, 2),
-                                           (512, 100, 101), (1024, 200, 21)])
+# n_x = 4^m runs the radix-4 kernel (16: outer and span-4 stages only), the
+# other powers of two the radix-2 kernel
+@pytest.mark.parametrize("n_x,n_t,n_out", [(8, 20, 5), (16, 40, 5), (32, 30, 4), (64, 200, 11),
+                                           (128, 60, 4), (256, 500, 2), (512, 100, 101),
+                                           (1024, 200, 21)])
 def test_solver_matches_oracle_across_grid_sizes(n_x, n_t, n_out):
     mus = np.concatenate([mu_cases(1, 3, 5), [[0, 0, 0], [0, 0, 2.0], [2.0, 2.0, 0.0]]])
     log(f"[case] cdr n_x={n_x} n_t={n_t} n_out={n_out} B={len(mus)}")
