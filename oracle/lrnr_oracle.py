@@ -535,9 +535,10 @@ def fast_loss_factored_bias(net, fast, s_list, B_list, sb_list, mu, pts, cfg=Non
 
 
 # --------------------------------------------------------------------------
-# Meta-learning of the coefficient map (Section 3.1, eq. 3.1-3.4) with the
-# bases U, V, b held fixed: the hypernetwork s = f_hyper(mu; Theta), the meta
-# loss averaged over parameter samples and the sparsity term R_sparse.
+# Meta-learning of the coefficient map and the biases (Section 3.1,
+# eq. 3.1-3.4) with the bases U, V held fixed: the hypernetwork
+# s = f_hyper(mu; Theta), the meta loss averaged over parameter samples and
+# the sparsity term R_sparse.
 # Readings: f_hyper is a network of the form of eq. 2.1 with the same
 # activation sigma = sin and a ReLU on its output; Theta is packed per layer
 # as W_k [H_k][H_{k-1}] row-major, then c_k [H_k]; the sigma inside R_sparse is
@@ -615,24 +616,30 @@ def hyper_backward(H, cache, s_bar):
     return np.concatenate([np.concatenate([gW.ravel(), gc]) for gW, gc in grads])
 
 
-def meta_objective(net, H, theta, mus, pts, gamma, lam_sparse, cfg=None, with_grad=False):
-    """Eq. 3.4 with the bases fixed: mean over the samples mu_b of the
+def meta_objective(net, H, theta, mus, pts, gamma, lam_sparse, cfg=None, with_grad=False,
+                   with_b=False):
+    """Eq. 3.4 with U and V fixed: mean over the samples mu_b of the
     physics-informed loss of the LRNR at s = f_hyper(mu_b; Theta) on the
-    shared points, plus lam_sparse * R_sparse.  Returns (objective, grad)."""
+    shared points, plus lam_sparse * R_sparse.  Returns (objective, grad
+    Theta), and with ``with_b`` also the gradient in the biases b (flat), the
+    mean over the samples of dL_b/db."""
     s, cache = hyper_forward(H, theta, mus)
     B = s.shape[0]
     tot = 0.0
     s_bar = np.zeros_like(s)
+    g_b = 0.0
     for b in range(B):
-        l4, gs, _ = lrnr_loss(net, net.split_s(s[b]), mus[b], pts, cfg, with_grad)
+        l4, gs, gb = lrnr_loss(net, net.split_s(s[b]), mus[b], pts, cfg, with_grad)
         tot = tot + l4[0] / B
         if with_grad:
             s_bar[b] = gs / B
+            g_b = g_b + gb / B
     obj = tot + lam_sparse * sparse_reg_value(s, net.r, gamma)
     if not with_grad:
-        return obj, None
+        return (obj, None, None) if with_b else (obj, None)
     s_bar = s_bar + lam_sparse * sparse_reg_grad(s, net.r, gamma) / B
-    return obj, hyper_backward(H, cache, s_bar)
+    g_theta = hyper_backward(H, cache, s_bar)
+    return (obj, g_theta, g_b) if with_b else (obj, g_theta)
 
 
 # --------------------------------------------------------------------------

@@ -524,6 +524,19 @@ def test_meta_objective_grad_complex_step():
     c = _complex_step_grad(lambda z: orc.meta_objective(net, H, z, mus, pts, 1.5, 0.3, cfg)[0],
                            theta)
     np.testing.assert_allclose(g, c, rtol=1e-10, atol=1e-13)
+    # the bias gradient of the same objective, against complex steps in b
+    _, _, gb = orc.meta_objective(net, H, theta, mus, pts, 1.5, 0.3, cfg, with_grad=True,
+                                  with_b=True)
+    import copy
+    sizes = [len(x) for x in net.b]
+
+    def ob(z):
+        n2 = copy.copy(net)
+        n2.b = orc._split(z, sizes)
+        return orc.meta_objective(n2, H, theta, mus, pts, 1.5, 0.3, cfg)[0]
+
+    cb = _complex_step_grad(ob, np.concatenate(net.b).astype(np.float64))
+    np.testing.assert_allclose(gb, cb, rtol=1e-10, atol=1e-13)
     # the objective is the mean of the per-sample losses plus the weighted term
     s, _ = orc.hyper_forward(H, theta, mus)
     per = [orc.lrnr_loss(net, net.split_s(s[b]), mus[b], pts, cfg)[0][0] for b in range(len(mus))]
