@@ -440,7 +440,8 @@ def run_reference(args, torch, api, wl, big):
 
 def run_meta(args, torch, api, wl):
     """Meta-learning of the coefficient map with fixed bases (Section 3.1,
-    eq. 3.1-3.4 without the basis updates): the small net, 64 parameter
+    eq. 3.1-3.4 without the basis updates), and of the map and the biases b
+    together (U, V fixed): the small net, 64 parameter
     samples sharing 16384 interior (+2048 IC, +2048 BC) points, hypernetwork
     widths (3, 33, 33, 33), R_sparse with gamma = 1.5 and weight 1e-3, Adam
     (lr 1e-3) on Theta for 200 steps.  Reported: ms per meta step (hypernetwork
@@ -486,6 +487,28 @@ def run_meta(args, torch, api, wl):
         loss, r = hist[i]
         return float(loss[:, 0].double().mean()) + lam * float(r[0])
 
+    # the same from the same start, training the biases b too (task table of
+    # GRAD tasks with per-sample grad_b, mean over the samples)
+    net_b = api.DeviceNet.from_net(w.net)
+    theta_b = torch.tensor(wl.hyper_init(H), device="cuda")
+    f_b = api.Hyper(H, theta_b)
+    meta_b = api.MetaStep(f_b, net_b, mu, pts)
+    mt, vt = torch.zeros_like(theta_b), torch.zeros_like(theta_b)
+    mb, vb = torch.zeros_like(net_b.b), torch.zeros_like(net_b.b)
+    hist_b = []
+    evb = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    evb[0].record()
+    for k in range(1, n_steps + 1):
+        g, gb, loss, r = meta_b(cfg, gamma, lam, ws=ws)
+        if k in (1, n_steps):
+            hist_b.append((loss.clone(), r.clone()))
+        api.adam_step(theta_b, mt, vt, g, k)
+        api.adam_step(net_b.b, mb, vb, gb, k)
+    evb[1].record()
+    torch.cuda.synchronize()
+    ms_b_step = evb[0].elapsed_time(evb[1]) / n_steps
+    obj_b = [float(l[:, 0].double().mean()) + lam * float(rr[0]) for l, rr in hist_b]
+
     n_r = pts.counts[0]
     return {
         "workload": "small net 64 wide x 4 hidden, rank 8; 64 mu samples sharing 16384 interior "
@@ -494,6 +517,8 @@ def run_meta(args, torch, api, wl):
         "ms_per_meta_step": ms, "pts_per_s": 64 * n_r / (ms * 1e-3),
         "hyper_forward_ms": ms_f, "batched_grad_ms": ms_g, "hyper_backward_ms": ms_b,
         "objective_first": obj(0), "objective_last": obj(1),
+        "with_biases": {"ms_per_meta_step": ms_b_step, "objective_first": obj_b[0],
+                        "objective_last": obj_b[1]},
         "theta_params": int(theta.numel()),
     }
 

@@ -497,6 +497,13 @@ int32_t lrnr_hyper_backward(const lrnr_hyper* f, const lrnr_net* net, int32_t B,
 /* Workspace bytes of lrnr_hyper_backward for B samples (0 if f or B is invalid). */
 size_t lrnr_hyper_workspace_size(const lrnr_hyper* f, int32_t B);
 
+/* Mean over samples, for the bias gradient of the meta objective (the biases
+ * are shared by all samples; eq. 3.4 averages over mu): out[e] = (1/B)
+ * sum_b x[b][e], summed in sample order in FP64 (bitwise reproducible).
+ *  x [dev] [B][n] (e.g. the grad_b rows of B GRAD tasks);  out [dev] [n].
+ * B >= 1; n may be 0. */
+int32_t lrnr_rows_mean(const float* x, int32_t B, int64_t n, float* out, void* stream);
+
 /*
  * Reference solution of the convection-diffusion-reaction problem of
  * Section 4, eq. 4.1 (u_t + mu_1 u_x - mu_2 u_xx - mu_3 u (1 - u) = 0 on

@@ -413,9 +413,10 @@ class Hyper:
         return C.byref(self._c)
 
 
-def hyper_forward(f, mu):
+def hyper_forward(f, mu, out=None):
     """s [B][r_total] = f_hyper(mu) for mu [B][3] (lrnr_hyper_forward)."""
-    s = torch.empty((mu.shape[0], f.H[-1]), dtype=torch.float32, device=mu.device)
+    s = out if out is not None else torch.empty((mu.shape[0], f.H[-1]), dtype=torch.float32,
+                                                device=mu.device)
     cl.check(cl.lib().lrnr_hyper_forward(f.c(), mu.shape[0], _p(mu), _p(s), _stream()),
              "lrnr_hyper_forward")
     return s
@@ -441,6 +442,43 @@ def meta_grad(f, net, mu, pts, cfg, gamma, lambda_sparse, ws=None):
     gs, loss = grad_s_batched(net, s, mu, pts, cfg, ws=ws)
     g, r = hyper_backward(f, net, mu, gs, gamma, lambda_sparse, ws=ws)
     return g, loss, r
+
+
+def rows_mean(x):
+    """(1/B) sum_b x[b] for x [B][n] (lrnr_rows_mean)."""
+    out = torch.empty(x.shape[1], dtype=torch.float32, device=x.device)
+    cl.check(cl.lib().lrnr_rows_mean(_p(x), x.shape[0], x.shape[1], _p(out), _stream()),
+             "lrnr_rows_mean")
+    return out
+
+
+class MetaStep:
+    """Gradient of the meta objective in Theta and in the biases b (eq. 3.4
+    with U, V fixed) for samples mu [B][3] sharing the points pts: s =
+    f_hyper(mu) into a task table of B GRAD tasks (per-sample grad_s and
+    grad_b), the hypernetwork backward, and the mean of the bias gradients.
+    The table is built once; the net's b may be updated in place between
+    calls."""
+
+    def __init__(self, f, net, mu, pts):
+        B, R = mu.shape[0], f.H[-1]
+        dev = mu.device
+        self.f, self.net, self.mu = f, net, mu
+        self.s = torch.empty((B, R), dtype=torch.float32, device=dev)
+        self.gs = torch.empty((B, R), dtype=torch.float32, device=dev)
+        self.gb = torch.empty((B, net.b_total), dtype=torch.float32, device=dev)
+        self.loss = torch.empty((B, 4), dtype=torch.float32, device=dev)
+        self.table = TaskTable([net])
+        for b in range(B):
+            self.table.add(0, s=self.s[b], mu=mu[b], xt_r=pts.xt_r, x_0=pts.x_0, t_b=pts.t_b,
+                           grad_s=self.gs[b], grad_b=self.gb[b], loss=self.loss[b])
+
+    def __call__(self, cfg, gamma, lambda_sparse, ws=None):
+        """Returns (grad_theta, grad_b, per-sample losses [B][4], R_sparse)."""
+        hyper_forward(self.f, self.mu, out=self.s)
+        self.table.run(MODE_GRAD, cfg, ws=ws, device=self.mu.device)
+        g, r = hyper_backward(self.f, self.net, self.mu, self.gs, gamma, lambda_sparse, ws=ws)
+        return g, rows_mean(self.gb), self.loss, r
 
 
 def cdr_reference(mu, n_x, n_t, n_out, t_end=1.0):

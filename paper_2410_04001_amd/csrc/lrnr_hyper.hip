@@ -160,6 +160,24 @@ __global__ void __launch_bounds__(kHyperThreads) hyper_sum_kernel(const float* w
     r_sparse[0] = (float)(acc / B);
 }
 
+// out[e] = (1/B) sum_b x[b][e] (b ascending, FP64, loads eight rows at a time)
+__global__ void __launch_bounds__(kHyperThreads) rows_mean_kernel(const float* x, int B,
+                                                                  int64_t n, float* out) {
+  const int64_t e = (int64_t)blockIdx.x * kHyperThreads + threadIdx.x;
+  if (e >= n) return;
+  double acc = 0.0;
+  int b = 0;
+  for (; b + 8 <= B; b += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = x[(int64_t)(b + u) * n + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += (double)v[u];
+  }
+  for (; b < B; ++b) acc += (double)x[(int64_t)b * n + e];
+  out[e] = (float)(acc / B);
+}
+
 int32_t make_khyper(const lrnr_hyper* f, KHyper* k) {
   if (!f) return fail(LRNR_EINVAL, "NULL hypernetwork");
   if (f->K < 1 || f->K > LRNR_MAX_LAYERS) return fail(LRNR_EINVAL, "hypernetwork K=%d", f->K);
@@ -245,6 +263,18 @@ int32_t lrnr_hyper_backward(const lrnr_hyper* f, const lrnr_net* net, int32_t B,
                      n_theta, grad_theta, r_sparse);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "hypernetwork sum launch");
+  return LRNR_OK;
+}
+
+int32_t lrnr_rows_mean(const float* x, int32_t B, int64_t n, float* out, void* stream) {
+  if (B < 1 || n < 0) return fail(LRNR_EINVAL, "B=%d n=%lld", B, (long long)n);
+  if (n == 0) return LRNR_OK;
+  if (!x || !out) return fail(LRNR_EINVAL, "NULL x or out");
+  const int64_t nb = (n + kHyperThreads - 1) / kHyperThreads;
+  hipLaunchKernelGGL(rows_mean_kernel, dim3((unsigned)nb), dim3(kHyperThreads), 0,
+                     static_cast<hipStream_t>(stream), x, B, n, out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "rows mean launch");
   return LRNR_OK;
 }
 

@@ -126,3 +126,28 @@ def test_hyper_depths_and_maximum_width(H_mid):
     g, r = a.hyper_backward(f, net, mu_d, torch.tensor(s_bar, device="cuda"), 2.0, 0.5)
     sb_ref = s_bar / 9 + 0.5 * orc.sparse_reg_grad(rs, w.net.r, 2.0) / 9
     assert_close(g.cpu().numpy(), orc.hyper_backward(H, cache, sb_ref), TOL, f"H={H} grad theta")
+
+
+def test_meta_step_with_biases_matches_oracle():
+    # Theta and bias gradients through a task table of GRAD tasks
+    a, w, H, theta, mus, f = setup(lambda: wl.small_lrnr(0, 2048), 5)
+    log("[case] meta step with biases, small net, B=5, N=2048")
+    net = a.DeviceNet.from_net(w.net)
+    pts = a.DevicePoints.from_points(w.pts)
+    step = a.MetaStep(f, net, torch.tensor(mus, device="cuda"), pts)
+    g, gb, loss, r = step(a.LossCfg(), 1.5, 0.3)
+    torch.cuda.synchronize()
+    obj, rg, rgb = orc.meta_objective(w.net, H, theta.astype(np.float64), mus.astype(np.float64),
+                                      w.pts, 1.5, 0.3, {}, with_grad=True, with_b=True)
+    got = float(loss[:, 0].double().mean()) + 0.3 * float(r[0])
+    assert abs(got - obj) <= TOL * abs(obj), (got, obj)
+    assert_close(g.cpu().numpy(), rg, TOL, "meta step grad theta")
+    assert_close(gb.cpu().numpy(), rgb, TOL, "meta step grad b")
+    # the mean over samples is a fixed-order sum
+    rng = np.random.Generator(np.random.PCG64(2))
+    x = rng.standard_normal((37, 1001)).astype(np.float32)
+    m1 = a.rows_mean(torch.tensor(x, device="cuda"))
+    m2 = a.rows_mean(torch.tensor(x, device="cuda"))
+    assert torch.equal(m1, m2)
+    np.testing.assert_allclose(m1.cpu().numpy(), x.astype(np.float64).mean(axis=0),
+                               rtol=1e-6, atol=1e-7)
