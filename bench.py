@@ -523,6 +523,101 @@ def run_meta(args, torch, api, wl):
     }
 
 
+def run_pipeline(args, torch, api, wl):
+    """The workflow of Section 3 on the small net (U, V fixed): (1) meta phase,
+    300 Adam steps (lr 1e-3) on the hypernetwork and the biases over 64
+    parameter samples (32 from each domain of Section 4) sharing the 65536
+    training points; (2) a FastLRNR (r_hat = 32) built from snapshots at
+    f_hyper of 8 of those samples; (3) for every bounded test case of the
+    reference leg, s_init = f_hyper(mu) and 200 Adam steps with the LRNR and
+    with the FastLRNR gradient, the L1 relative error against the reference
+    solution every 20 steps against the summed step time."""
+    n_x, n_t, n_out, n_steps, every = 256, 1000, 101, 200, 20
+    w = wl.equal_accuracy_case(big=False)
+    net = api.DeviceNet.from_net(w.net)
+    pts = api.DevicePoints.from_points(w.pts)
+    cfg = api.LossCfg()
+    ws = api.Workspace()
+    R = w.net.r_total
+    H = [3, R, R, R]
+    f = api.Hyper(H, torch.tensor(wl.hyper_init(H), device="cuda"))
+    mu_tr = torch.tensor(wl.cdr_test_cases(8, 32, 32).astype(np.float32), device="cuda")
+    meta = api.MetaStep(f, net, mu_tr, pts)
+    mt, vt = torch.zeros_like(f.theta), torch.zeros_like(f.theta)
+    mb, vb = torch.zeros_like(net.b), torch.zeros_like(net.b)
+    t0 = time.time()
+    objs = []
+    for k in range(1, 301):
+        g, gb, loss, r = meta(cfg, 1.5, 1e-3, ws=ws)
+        if k in (1, 300):
+            objs.append(float(loss[:, 0].double().mean()) + 1e-3 * float(r[0]))
+        api.adam_step(f.theta, mt, vt, g, k)
+        api.adam_step(net.b, mb, vb, gb, k)
+    torch.cuda.synchronize()
+    meta_s = time.time() - t0
+    s_snap = api.hyper_forward(f, mu_tr[::8].contiguous())
+    fast = api.FastLRNR(net, s_snap, torch.tensor(w.extra["xt_snap"], device="cuda"),
+                        w.extra["r_hat"])
+    mus = wl.cdr_test_cases()
+    u_ref, st = api.cdr_reference(torch.tensor(mus, device="cuda"), n_x, n_t, n_out)
+    st = st.cpu().numpy()
+    xt = torch.tensor(wl.grid_points(n_x, n_out), device="cuda")
+    sums = torch.empty(2, dtype=torch.float64, device="cuda")
+
+    def l1(s, ref):
+        api.l1_error_sums(api.forward_value(net, s, xt), ref, out=sums)
+        a, b = sums.cpu().numpy()
+        return float(a / b)
+
+    def train(grad_fn, s0, ref):
+        s = s0.clone()
+        m, v = torch.zeros_like(s), torch.zeros_like(s)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(n_steps)]
+        errs = [l1(s, ref)]
+        for k in range(1, n_steps + 1):
+            evs[k - 1][0].record()
+            api.adam_step(s, m, v, grad_fn(s), k)
+            evs[k - 1][1].record()
+            if k % every == 0:
+                errs.append(l1(s, ref))
+        torch.cuda.synchronize()
+        t = np.cumsum([a.elapsed_time(b) for a, b in evs])
+        return errs, [0.0] + [float(t[k - 1]) for k in range(every, n_steps + 1, every)]
+
+    cases, warm = [], True
+    for i, mu in enumerate(mus):
+        if st[i]:
+            continue
+        mu32 = torch.tensor(mu.astype(np.float32), device="cuda")
+        s0 = api.hyper_forward(f, mu32.reshape(1, 3))[0].contiguous()
+        ref = u_ref[i].reshape(-1)
+        lg = lambda s: api.grad_s(net, s, mu32, pts, cfg, with_b=False, ws=ws)[0]
+        fg = lambda s: fast.grad_s(s, mu32, pts, cfg, ws=ws)[0]
+        if warm:
+            train(lg, s0, ref)
+            train(fg, s0, ref)
+            warm = False
+        el, tl = train(lg, s0, ref)
+        ef, tf = train(fg, s0, ref)
+        cases.append({"mu": mu.tolist(), "l1_meta_init": el[0], "lrnr_l1": el, "lrnr_ms": tl,
+                      "fastlrnr_l1": ef, "fastlrnr_ms": tf})
+    fast.close()
+    init = [c["l1_meta_init"] for c in cases]
+    return {
+        "workload": "small net 64 wide x 4 hidden, rank 8, U and V fixed; meta phase 300 steps "
+                    "over 64 samples of the Section 4 domains (Theta and b); FastLRNR r_hat=32 "
+                    "from 8 meta samples; 200 fine-tuning steps per bounded test case",
+        "meta_objective_first": objs[0], "meta_objective_last": objs[1], "meta_phase_s": meta_s,
+        "l1_meta_init_median": float(np.median(init)),
+        "l1_lrnr_final_median": float(np.median([c["lrnr_l1"][-1] for c in cases])),
+        "l1_fastlrnr_final_median": float(np.median([c["fastlrnr_l1"][-1] for c in cases])),
+        "lrnr_ms_200_median": float(np.median([c["lrnr_ms"][-1] for c in cases])),
+        "fastlrnr_ms_200_median": float(np.median([c["fastlrnr_ms"][-1] for c in cases])),
+        "cases": cases,
+    }
+
+
 def cpu_reference_solver(wl):
     """The oracle's reference solver on the same 20 test parameters (numpy FFT
     Strang splitting, FP64), one pass."""
@@ -716,6 +811,7 @@ def main():
     ap.add_argument("--no-reference", action="store_true")
     ap.add_argument("--no-bias", action="store_true")
     ap.add_argument("--no-meta", action="store_true")
+    ap.add_argument("--no-pipeline", action="store_true")
     ap.add_argument("--serve-rates", type=lambda x: [float(v) for v in x.split(",")],
                     default=[50, 100, 200, 500, 1000, 2000])
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -785,6 +881,8 @@ def main():
         out["reference"] = [run_reference(args, torch, api, wl, big) for big in (False, True)]
     if not args.no_meta:
         out["meta"] = run_meta(args, torch, api, wl)
+    if not args.no_pipeline:
+        out["pipeline"] = run_pipeline(args, torch, api, wl)
     if not args.no_diff:
         out["differentiation"] = run_differentiation(args, torch, api, wl)
     if not args.no_serve:
