@@ -616,6 +616,22 @@ def hyper_backward(H, cache, s_bar):
     return np.concatenate([np.concatenate([gW.ravel(), gc]) for gW, gc in grads])
 
 
+def orth_reg(U_list, V_list, with_grad=False):
+    """R_orth of eq. 3.3: sum_l ||U^lT U^l - I||_F^2 + ||V^lT V^l - I||_F^2.
+    With ``with_grad`` also its gradients 4 U (U^T U - I) and 4 V (V^T V - I)
+    per layer."""
+    val = 0.0
+    gU, gV = [], []
+    for M in (U_list, V_list):
+        for A in M:
+            A = _f(A)
+            D = A.T @ A - np.eye(A.shape[1])
+            val = val + np.sum(D * D)
+            if with_grad:
+                (gU if M is U_list else gV).append(4.0 * A @ D)
+    return (val, gU, gV) if with_grad else val
+
+
 def meta_objective(net, H, theta, mus, pts, gamma, lam_sparse, cfg=None, with_grad=False,
                    with_b=False):
     """Eq. 3.4 with U and V fixed: mean over the samples mu_b of the

@@ -541,3 +541,30 @@ def test_meta_objective_grad_complex_step():
     s, _ = orc.hyper_forward(H, theta, mus)
     per = [orc.lrnr_loss(net, net.split_s(s[b]), mus[b], pts, cfg)[0][0] for b in range(len(mus))]
     assert obj == pytest.approx(np.mean(per) + 0.3 * orc.sparse_reg_value(s, net.r, 1.5), rel=1e-14)
+
+
+def test_orth_reg_zero_on_orthonormal_bases_and_complex_step():
+    net, _, _ = tiny_case()
+    # the generators column-orthonormalise U and V: R_orth vanishes (to FP32
+    # rounding of the stored factors)
+    assert orc.orth_reg(net.U, net.V) < 1e-11
+    # a hand value: U = 2 I (2 x 2) gives ||4 I - I||^2 = 18, V = [1, 1]^T gives (2 - 1)^2 = 1
+    assert orc.orth_reg([2 * np.eye(2)], [np.ones((2, 1))]) == pytest.approx(19.0)
+    rng = np.random.default_rng(3)
+    U = [rng.standard_normal((5, 3)), rng.standard_normal((4, 2))]
+    V = [rng.standard_normal((3, 3)), rng.standard_normal((5, 2))]
+    _, gU, gV = orc.orth_reg(U, V, with_grad=True)
+    flat = np.concatenate([a.ravel() for a in U + V])
+    shapes = [a.shape for a in U + V]
+
+    def f(z):
+        out, o = [], 0
+        for sh in shapes:
+            n = sh[0] * sh[1]
+            out.append(z[o:o + n].reshape(sh))
+            o += n
+        return orc.orth_reg(out[:2], out[2:])
+
+    c = _complex_step_grad(f, flat)
+    np.testing.assert_allclose(np.concatenate([a.ravel() for a in gU + gV]), c, rtol=1e-12,
+                               atol=1e-13)
