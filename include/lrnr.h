@@ -497,6 +497,15 @@ int32_t lrnr_hyper_backward(const lrnr_hyper* f, const lrnr_net* net, int32_t B,
 /* Workspace bytes of lrnr_hyper_backward for B samples (0 if f or B is invalid). */
 size_t lrnr_hyper_workspace_size(const lrnr_hyper* f, int32_t B);
 
+/* Orthogonality term of eq. 3.3 on the net's bases:
+ *   R_orth = sum_l ||U^lT U^l - I||_F^2 + ||V^lT V^l - I||_F^2  (all L layers),
+ * and its gradients 4 U^l (U^lT U^l - I), 4 V^l (V^lT V^l - I).
+ *  value  [dev] [1] out, may be NULL
+ *  grad_U [dev] packed as net.U, out, may be NULL;  grad_V as net.V, may be NULL
+ * FP64 sums in a fixed order (one workgroup). */
+int32_t lrnr_orth_reg(const lrnr_net* net, float* value, float* grad_U, float* grad_V,
+                      void* stream);
+
 /* Mean over samples, for the bias gradient of the meta objective (the biases
  * are shared by all samples; eq. 3.4 averages over mu): out[e] = (1/B)
  * sum_b x[b][e], summed in sample order in FP64 (bitwise reproducible).

@@ -452,6 +452,18 @@ def rows_mean(x):
     return out
 
 
+def orth_reg(net, with_grad=True):
+    """R_orth of eq. 3.3 on the net's bases (lrnr_orth_reg): (value [1],
+    grad_U, grad_V) device tensors (the gradients None without with_grad)."""
+    v = torch.empty(1, dtype=torch.float32, device="cuda")
+    gU = torch.empty(sum(net.M[l] * net.r[l - 1] for l in range(1, net.L + 1)),
+                     dtype=torch.float32, device="cuda") if with_grad else None
+    gV = torch.empty(sum(net.M[l - 1] * net.r[l - 1] for l in range(1, net.L + 1)),
+                     dtype=torch.float32, device="cuda") if with_grad else None
+    cl.check(cl.lib().lrnr_orth_reg(net.c(), _p(v), _p(gU), _p(gV), _stream()), "lrnr_orth_reg")
+    return v, gU, gV
+
+
 class MetaStep:
     """Gradient of the meta objective in Theta and in the biases b (eq. 3.4
     with U, V fixed) for samples mu [B][3] sharing the points pts: s =

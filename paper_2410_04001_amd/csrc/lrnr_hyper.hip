@@ -178,6 +178,51 @@ __global__ void __launch_bounds__(kHyperThreads) rows_mean_kernel(const float* x
   out[e] = (float)(acc / B);
 }
 
+// R_orth of eq. 3.3 over every factor A (U^l [M_l][r_l], V^l [M_{l-1}][r_l]):
+// D = A^T A - I, value += ||D||_F^2, grad A = 4 A D.  One workgroup walks the
+// factors in order (a few hundred thousand multiply-adds), FP64 sums.
+constexpr int kOrthThreads = 1024;
+
+__global__ void __launch_bounds__(kOrthThreads) orth_reg_kernel(KNet k, float* value,
+                                                                float* gU, float* gV) {
+  __shared__ double D[LRNR_MAX_RANK * LRNR_MAX_RANK];
+  __shared__ double red[kOrthThreads];
+  const int tid = threadIdx.x;
+  double vsum = 0.0;
+  for (int f = 0; f < 2 * k.L; ++f) {
+    const int l = f / 2 + 1;
+    const bool isU = (f & 1) == 0;
+    const int M = isU ? k.M[l] : k.M[l - 1], r = k.r[l];
+    const float* A = isU ? k.U + k.offU[l] : k.V + k.offV[l];
+    float* G = isU ? (gU ? gU + k.offU[l] : nullptr) : (gV ? gV + k.offV[l] : nullptr);
+    for (int e = tid; e < r * r; e += kOrthThreads) {
+      const int i = e / r, j = e - i * r;
+      double acc = 0.0;
+      for (int m = 0; m < M; ++m) acc += (double)A[m * r + i] * (double)A[m * r + j];
+      const double d = acc - (i == j ? 1.0 : 0.0);
+      D[e] = d;
+      vsum += d * d;
+    }
+    __syncthreads();
+    if (G) {
+      for (int e = tid; e < M * r; e += kOrthThreads) {
+        const int m = e / r, c = e - m * r;
+        double acc = 0.0;
+        for (int j = 0; j < r; ++j) acc += (double)A[m * r + j] * D[j * r + c];
+        G[e] = (float)(4.0 * acc);
+      }
+    }
+    __syncthreads();
+  }
+  red[tid] = vsum;
+  __syncthreads();
+  for (int w = kOrthThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0 && value) value[0] = (float)red[0];
+}
+
 int32_t make_khyper(const lrnr_hyper* f, KHyper* k) {
   if (!f) return fail(LRNR_EINVAL, "NULL hypernetwork");
   if (f->K < 1 || f->K > LRNR_MAX_LAYERS) return fail(LRNR_EINVAL, "hypernetwork K=%d", f->K);
@@ -275,6 +320,20 @@ int32_t lrnr_rows_mean(const float* x, int32_t B, int64_t n, float* out, void* s
                      static_cast<hipStream_t>(stream), x, B, n, out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "rows mean launch");
+  return LRNR_OK;
+}
+
+int32_t lrnr_orth_reg(const lrnr_net* net, float* value, float* grad_U, float* grad_V,
+                      void* stream) {
+  KNet k;
+  int RP, Wp;
+  int32_t rc = make_knet(net, &k, &RP, &Wp);
+  if (rc != LRNR_OK) return rc;
+  if (!value && !grad_U && !grad_V) return LRNR_OK;
+  hipLaunchKernelGGL(orth_reg_kernel, dim3(1), dim3(kOrthThreads), 0,
+                     static_cast<hipStream_t>(stream), k, value, grad_U, grad_V);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "orthogonality term launch");
   return LRNR_OK;
 }
 

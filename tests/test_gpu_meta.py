@@ -151,3 +151,23 @@ def test_meta_step_with_biases_matches_oracle():
     assert torch.equal(m1, m2)
     np.testing.assert_allclose(m1.cpu().numpy(), x.astype(np.float64).mean(axis=0),
                                rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("name,make", NETS, ids=[n for n, _ in NETS])
+def test_orth_reg_matches_oracle(name, make):
+    import copy
+    a = api()
+    w = make()
+    rng = np.random.Generator(np.random.PCG64(13))
+    n2 = copy.copy(w.net)          # bases pulled off orthonormality
+    n2.U = [(u * (1 + 0.2 * rng.standard_normal(u.shape))).astype(np.float32) for u in w.net.U]
+    n2.V = [(v * (1 + 0.2 * rng.standard_normal(v.shape))).astype(np.float32) for v in w.net.V]
+    log(f"[case] R_orth {name}")
+    v, gU, gV = a.orth_reg(a.DeviceNet.from_net(n2))
+    rv, rgU, rgV = orc.orth_reg(n2.U, n2.V, with_grad=True)
+    assert abs(float(v[0]) - rv) <= TOL * rv, (float(v[0]), rv)
+    assert_close(gU.cpu().numpy(), np.concatenate([g.ravel() for g in rgU]), TOL, f"{name} grad U")
+    assert_close(gV.cpu().numpy(), np.concatenate([g.ravel() for g in rgV]), TOL, f"{name} grad V")
+    # the generated bases are orthonormal up to FP32 rounding
+    v0, _, _ = a.orth_reg(a.DeviceNet.from_net(w.net), with_grad=False)
+    assert float(v0[0]) < 1e-9
