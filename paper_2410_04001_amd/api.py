@@ -14,7 +14,14 @@ from . import _clib as cl
 
 
 def _p(t):
-    return None if t is None else C.c_void_p(t.data_ptr())
+    """Device address of a tensor for the C ABI, whose arrays are all device
+    memory: a host tensor here would reach a kernel as a bad address, so it is
+    refused."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("a device (cuda) tensor is required, got one on " + str(t.device))
+    return C.c_void_p(t.data_ptr())
 
 
 def _stream():

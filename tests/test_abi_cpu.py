@@ -225,3 +225,13 @@ def test_serving_footprint_and_config_validation(lib):
         assert lib.lrnr_srv_footprint(C.byref(c), 0, 1024, 128, 128) == 0, bad
     models[1].s_init = None
     assert lib.lrnr_srv_footprint(C.byref(cfg), 0, 1024, 128, 128) == 0
+
+
+def test_host_tensors_are_refused_at_the_boundary():
+    # every array of the C ABI is device memory; a host tensor is refused
+    # before any call is made
+    torch = pytest.importorskip("torch")
+    from paper_2410_04001_amd import api
+    with pytest.raises(ValueError):
+        api._p(torch.zeros(4))
+    assert api._p(None) is None
