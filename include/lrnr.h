@@ -497,6 +497,26 @@ int32_t lrnr_hyper_backward(const lrnr_hyper* f, const lrnr_net* net, int32_t B,
 /* Workspace bytes of lrnr_hyper_backward for B samples (0 if f or B is invalid). */
 size_t lrnr_hyper_workspace_size(const lrnr_hyper* f, int32_t B);
 
+/*
+ * Gradient of the physics-informed loss (eq. 3.5 / 3.6 with eq. 4.1; the
+ * locality term does not depend on the bases) with respect to the bases, the
+ * parameters the meta-learning phase trains besides Theta and b (eq. 3.4):
+ *   grad_U^l = sum_p sum_c abar^l_{p,c} (s^l * y^l_{p,c})^T,
+ *   grad_V^l = sum_p sum_c z^{l-1}_{p,c} ybar^l_{p,c}^T   (c over the jets).
+ *  grad_U [dev] packed as net.U, out;  grad_V [dev] packed as net.V, out
+ *  ws [dev] workspace of lrnr_basis_grad_workspace_size bytes: per-point
+ *  jets and adjoints, about 4 (3 sum_l M_l + 2 sum_l r_l) floats per point.
+ * Other arguments as lrnr_grad_s.  Not the hot path: one thread per point,
+ * FP32, then a fixed-order FP64 sum over the points per entry (bitwise
+ * reproducible).  LRNR_ENOMEM on a short workspace.
+ */
+int32_t lrnr_basis_grad(const lrnr_net* net, const float* s, const float* mu,
+                        const lrnr_points* pts, const lrnr_loss_cfg* cfg, float* grad_U,
+                        float* grad_V, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes of lrnr_basis_grad (0 when the net or points are invalid). */
+size_t lrnr_basis_grad_workspace_size(const lrnr_net* net, const lrnr_points* pts);
+
 /* Orthogonality term of eq. 3.3 on the net's bases:
  *   R_orth = sum_l ||U^lT U^l - I||_F^2 + ||V^lT V^l - I||_F^2  (all L layers),
  * and its gradients 4 U^l (U^lT U^l - I), 4 V^l (V^lT V^l - I).

@@ -616,6 +616,22 @@ def hyper_backward(H, cache, s_bar):
     return np.concatenate([np.concatenate([gW.ravel(), gc]) for gW, gc in grads])
 
 
+def lrnr_basis_grad(net, s_list, mu, pts, cfg=None):
+    """Gradient of the loss with respect to U^l and V^l (flat, packed per
+    layer): from the dense weight gradient gW^l of eq. 2.1 and W^l =
+    U^l diag(s^l) V^lT (eq. 2.2), dL/dU^l = gW^l V^l diag(s^l) and
+    dL/dV^l = gW^lT U^l diag(s^l)."""
+    cfg = cfg or {}
+    W = dense_weights(net.U, s_list, net.V)
+    X, n_r, n_0, n_b = _all_points(pts)
+    jets, cache = mlp_forward(W, net.b, X)
+    _, ubar = _loss_and_ubar(jets, n_r, n_0, n_b, _f(pts.x_0), mu, cfg)
+    gW, _ = mlp_backward(W, cache, ubar)
+    gU = [g @ _f(V) * _f(s)[None, :] for g, V, s in zip(gW, net.V, s_list)]
+    gV = [g.T @ _f(U) * _f(s)[None, :] for g, U, s in zip(gW, net.U, s_list)]
+    return np.concatenate([g.ravel() for g in gU]), np.concatenate([g.ravel() for g in gV])
+
+
 def orth_reg(U_list, V_list, with_grad=False):
     """R_orth of eq. 3.3: sum_l ||U^lT U^l - I||_F^2 + ||V^lT V^l - I||_F^2.
     With ``with_grad`` also its gradients 4 U (U^T U - I) and 4 V (V^T V - I)

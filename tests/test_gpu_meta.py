@@ -171,3 +171,26 @@ def test_orth_reg_matches_oracle(name, make):
     # the generated bases are orthonormal up to FP32 rounding
     v0, _, _ = a.orth_reg(a.DeviceNet.from_net(w.net), with_grad=False)
     assert float(v0[0]) < 1e-9
+
+
+@pytest.mark.parametrize("name,make,form", [("small", lambda: wl.small_lrnr(0, 2048), 0),
+                                            ("small_l1", lambda: wl.small_lrnr(0, 1500), 1),
+                                            ("wide", lambda: wl.big_lrnr(1, 512), 0)],
+                         ids=["small", "small_l1", "wide"])
+def test_basis_grad_matches_oracle(name, make, form):
+    a = api()
+    w = make()
+    log(f"[case] basis gradient {name}: M={w.net.M} r={w.net.r} form={form}")
+    net = a.DeviceNet.from_net(w.net)
+    s = torch.tensor(w.net.s_flat(), device="cuda")
+    pts = a.DevicePoints.from_points(w.pts)
+    mu = torch.tensor(w.mu[0], device="cuda")
+    cfg = a.LossCfg(form=form, w_0=0.7, w_b=1.3)
+    gU, gV = a.basis_grad(net, s, mu, pts, cfg)
+    gU2, gV2 = a.basis_grad(net, s, mu, pts, cfg)
+    torch.cuda.synchronize()
+    rU, rV = orc.lrnr_basis_grad(w.net, w.net.s, w.mu[0].astype(np.float64), w.pts,
+                                 {"form": form, "w_r": 1.0, "w_0": 0.7, "w_b": 1.3})
+    assert_close(gU.cpu().numpy(), rU, TOL, f"{name} grad U")
+    assert_close(gV.cpu().numpy(), rV, TOL, f"{name} grad V")
+    assert torch.equal(gU, gU2) and torch.equal(gV, gV2)

@@ -568,3 +568,26 @@ def test_orth_reg_zero_on_orthonormal_bases_and_complex_step():
     c = _complex_step_grad(f, flat)
     np.testing.assert_allclose(np.concatenate([a.ravel() for a in gU + gV]), c, rtol=1e-12,
                                atol=1e-13)
+
+
+def test_basis_grad_complex_step():
+    net, pts, mu = tiny_case(n=20)
+    cfg = {"form": 0, "w_r": 1.0, "w_0": 0.7, "w_b": 1.3}
+    gU, gV = orc.lrnr_basis_grad(net, net.s, mu, pts, cfg)
+    import copy
+    for attr, g in (("U", gU), ("V", gV)):
+        mats = getattr(net, attr)
+        shapes = [m.shape for m in mats]
+
+        def f(z, attr=attr, shapes=shapes):
+            n2 = copy.copy(net)
+            out, o = [], 0
+            for sh in shapes:
+                k = sh[0] * sh[1]
+                out.append(z[o:o + k].reshape(sh))
+                o += k
+            setattr(n2, attr, out)
+            return orc.lrnr_loss(n2, net.s, mu, pts, cfg)[0][0]
+
+        c = _complex_step_grad(f, np.concatenate([m.ravel() for m in mats]).astype(np.float64))
+        np.testing.assert_allclose(g, c, rtol=1e-10, atol=1e-13)
