@@ -509,6 +509,40 @@ def run_meta(args, torch, api, wl):
     ms_b_step = evb[0].elapsed_time(evb[1]) / n_steps
     obj_b = [float(l[:, 0].double().mean()) + lam * float(rr[0]) for l, rr in hist_b]
 
+    # all of eq. 3.4: Theta, b, U and V (basis gradient per sample, its mean,
+    # and R_orth with weight 1e-3) on 8 of the samples, 30 steps
+    net_u = api.DeviceNet.from_net(w.net)
+    theta_u = torch.tensor(wl.hyper_init(H), device="cuda")
+    f_u = api.Hyper(H, theta_u)
+    mu8 = mu[:8].contiguous()
+    meta_u = api.MetaStep(f_u, net_u, mu8, pts)
+    lam_o = 1e-3
+    params = [theta_u, net_u.b, net_u.U, net_u.V]
+    mom = [(torch.zeros_like(p), torch.zeros_like(p)) for p in params]
+    hist_u = []
+    evu = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    evu[0].record()
+    n_u = 30
+    for k in range(1, n_u + 1):
+        g, gb, loss, r = meta_u(cfg, gamma, lam, ws=ws)
+        gUs, gVs = [], []
+        for j in range(8):
+            gU_j, gV_j = api.basis_grad(net_u, meta_u.s[j], mu8[j], pts, cfg, ws=ws)
+            gUs.append(gU_j)
+            gVs.append(gV_j)
+        ro, gUo, gVo = api.orth_reg(net_u)
+        gU = api.rows_mean(torch.stack(gUs)) + lam_o * gUo
+        gV = api.rows_mean(torch.stack(gVs)) + lam_o * gVo
+        if k in (1, n_u):
+            hist_u.append((loss.clone(), r.clone(), ro.clone()))
+        for p_, (m_, v_), g_ in zip(params, mom, (g, gb, gU, gV)):
+            api.adam_step(p_, m_, v_, g_, k)
+    evu[1].record()
+    torch.cuda.synchronize()
+    ms_u_step = evu[0].elapsed_time(evu[1]) / n_u
+    obj_u = [float(l[:, 0].double().mean()) + lam * float(rr[0]) + lam_o * float(oo[0])
+             for l, rr, oo in hist_u]
+
     n_r = pts.counts[0]
     return {
         "workload": "small net 64 wide x 4 hidden, rank 8; 64 mu samples sharing 16384 interior "
@@ -519,6 +553,9 @@ def run_meta(args, torch, api, wl):
         "objective_first": obj(0), "objective_last": obj(1),
         "with_biases": {"ms_per_meta_step": ms_b_step, "objective_first": obj_b[0],
                         "objective_last": obj_b[1]},
+        "with_bases_8_samples_30_steps": {"ms_per_meta_step": ms_u_step,
+                                          "objective_first": obj_u[0],
+                                          "objective_last": obj_u[1], "lambda_orth": lam_o},
         "theta_params": int(theta.numel()),
     }
 
