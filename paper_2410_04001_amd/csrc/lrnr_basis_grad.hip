@@ -6,9 +6,9 @@
 // pre-activation of layer l, y^l = V^lT z^{l-1} its reduced input and ybar^l
 // the adjoint of y^l.  Not the hot path: one thread per evaluation point runs
 // the forward and reverse jets and leaves w = s * y, a, abar and ybar in a
-// caller workspace; a second kernel forms every entry of the two gradients
-// as a sum over the points in a fixed order (FP64), so the result is
-// bitwise reproducible.
+// caller workspace; every entry of the two gradients is then a sum over the
+// points, taken as partial sums over fixed chunks of points and a sum of the
+// chunks in order (FP64), so the result is bitwise reproducible.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -18,7 +18,9 @@
 namespace lrnr {
 namespace {
 
-constexpr int kBgThreads = 256;
+constexpr int kBgThreads = 64;    // per-point kernels: more workgroups, more CUs busy
+constexpr int kBgSumThreads = 256;
+constexpr int kBgChunks = 64;     // point chunks of the contraction
 constexpr float kTwoPi = 6.28318530717958647692f;
 
 struct KBg {
@@ -37,6 +39,9 @@ struct KBg {
   float* Abar[LRNR_MAX_LAYERS + 1];   // abar^l, dim M_l (l = 1..L)
   float* Ybar[LRNR_MAX_LAYERS + 1];   // ybar^l, dim r_l (l = 1..L)
   float* Ujet;                        // [E][4]
+  double* part;                       // [chunks][n_out] partial sums
+  int chunks;
+  int64_t n_out;
 };
 
 __device__ inline void point_xt(const KBg& g, int64_t e, float& x, float& t) {
@@ -221,13 +226,8 @@ __global__ void __launch_bounds__(kBgThreads) bg_reverse_kernel(KBg g) {
   }
 }
 
-// One thread per gradient entry: U^l[i][j] = sum_e sum_c Abar[e][c][i] W[e][c][j],
-// V^l[i][j] = sum_e sum_c Z^{l-1}[e][c][i] Ybar[e][c][j], e ascending, FP64.
-__global__ void __launch_bounds__(kBgThreads) bg_contract_kernel(KBg g, float* gU, float* gV) {
-  const KNet& k = g.k;
-  int64_t id = (int64_t)blockIdx.x * kBgThreads + threadIdx.x;
-  int l = 1;
-  bool isU = true;
+// Gradient entry id -> layer, U or V, row and column (U^l then V^l, l = 1..L).
+__device__ inline bool bg_decode(const KNet& k, int64_t id, int& l, bool& isU, int& i, int& j) {
   int64_t rem = id;
   for (l = 1; l <= k.L; ++l) {
     const int64_t nu = (int64_t)k.M[l] * k.r[l], nv = (int64_t)k.M[l - 1] * k.r[l];
@@ -242,22 +242,35 @@ __global__ void __launch_bounds__(kBgThreads) bg_contract_kernel(KBg g, float* g
     }
     rem -= nv;
   }
-  if (l > k.L) return;
+  if (l > k.L) return false;
+  i = (int)(rem / k.r[l]);
+  j = (int)(rem - (int64_t)i * k.r[l]);
+  return true;
+}
+
+// Partial sums over chunk blockIdx.y of the points, one thread per gradient
+// entry: U^l[i][j] += Abar[e][c][i] W[e][c][j], V^l[i][j] += Z^{l-1}[e][c][i]
+// Ybar[e][c][j], points ascending within the chunk, FP64.
+__global__ void __launch_bounds__(kBgSumThreads) bg_contract_kernel(KBg g) {
+  const KNet& k = g.k;
+  const int64_t id = (int64_t)blockIdx.x * kBgSumThreads + threadIdx.x;
+  int l, i, j;
+  bool isU;
+  if (id >= g.n_out || !bg_decode(k, id, l, isU, i, j)) return;
+  const int64_t e0 = g.E * blockIdx.y / g.chunks, e1 = g.E * (blockIdx.y + 1) / g.chunks;
   const int rl = k.r[l];
-  const int i = (int)(rem / rl), j = (int)(rem - (int64_t)i * rl);
   double acc = 0.0;
   if (isU) {
     const int M = k.M[l];
     const float* Ab = g.Abar[l];
     const float* W = g.W[l];
-    for (int64_t e = 0; e < g.E; ++e)
+    for (int64_t e = e0; e < e1; ++e)
 #pragma unroll
       for (int c = 0; c < 4; ++c)
         acc += (double)Ab[(e * 4 + c) * M + i] * (double)W[(e * 4 + c) * rl + j];
-    gU[k.offU[l] + i * rl + j] = (float)acc;
   } else {
     const float* Yb = g.Ybar[l];
-    for (int64_t e = 0; e < g.E; ++e) {
+    for (int64_t e = e0; e < e1; ++e) {
       float z[4];
       if (l == 1) {
         float x, t;
@@ -279,8 +292,24 @@ __global__ void __launch_bounds__(kBgThreads) bg_contract_kernel(KBg g, float* g
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc += (double)z[c] * (double)Yb[(e * 4 + c) * rl + j];
     }
-    gV[k.offV[l] + i * rl + j] = (float)acc;
   }
+  g.part[(int64_t)blockIdx.y * g.n_out + id] = acc;
+}
+
+// Sum of the chunks in order, into grad_U / grad_V.
+__global__ void __launch_bounds__(kBgSumThreads) bg_sum_kernel(KBg g, float* gU, float* gV) {
+  const KNet& k = g.k;
+  const int64_t id = (int64_t)blockIdx.x * kBgSumThreads + threadIdx.x;
+  int l, i, j;
+  bool isU;
+  if (id >= g.n_out || !bg_decode(k, id, l, isU, i, j)) return;
+  double acc = 0.0;
+  for (int c = 0; c < g.chunks; ++c) acc += g.part[(int64_t)c * g.n_out + id];
+  const int rl = k.r[l];
+  if (isU)
+    gU[k.offU[l] + i * rl + j] = (float)acc;
+  else
+    gV[k.offV[l] + i * rl + j] = (float)acc;
 }
 
 // workspace floats of each array (and the total), for E points
@@ -298,6 +327,11 @@ int64_t bg_layout(const KNet& k, int64_t E, KBg* g, float* base) {
     g->A[l] = (l < k.L) ? take(E * 4 * k.M[l]) : nullptr;
   }
   g->Ujet = take(E * 4);
+  int64_t n_out = 0;
+  for (int l = 1; l <= k.L; ++l) n_out += (int64_t)(k.M[l] + k.M[l - 1]) * k.r[l];
+  g->n_out = n_out;
+  g->chunks = (int)(E / 256 < kBgChunks ? (E / 256 > 0 ? E / 256 : 1) : kBgChunks);
+  g->part = reinterpret_cast<double*>(take(2 * (int64_t)g->chunks * n_out));
   return o;
 }
 
@@ -354,12 +388,13 @@ int32_t lrnr_basis_grad(const lrnr_net* net, const float* s, const float* mu,
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "basis gradient reverse launch");
   }
-  int64_t n_out = 0;
-  for (int l = 1; l <= g.k.L; ++l) n_out += (int64_t)(g.k.M[l] + g.k.M[l - 1]) * g.k.r[l];
-  const unsigned nc = (unsigned)((n_out + kBgThreads - 1) / kBgThreads);
-  hipLaunchKernelGGL(bg_contract_kernel, dim3(nc), dim3(kBgThreads), 0, st, g, grad_U, grad_V);
+  const unsigned nc = (unsigned)((g.n_out + kBgSumThreads - 1) / kBgSumThreads);
+  hipLaunchKernelGGL(bg_contract_kernel, dim3(nc, g.chunks), dim3(kBgSumThreads), 0, st, g);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "basis gradient contraction launch");
+  hipLaunchKernelGGL(bg_sum_kernel, dim3(nc), dim3(kBgSumThreads), 0, st, g, grad_U, grad_V);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "basis gradient sum launch");
   return LRNR_OK;
 }
 
