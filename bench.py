@@ -561,10 +561,11 @@ def run_meta(args, torch, api, wl):
 
 
 def run_pipeline(args, torch, api, wl):
-    """The workflow of Section 3 on the small net (U, V fixed): (1) meta phase,
-    300 Adam steps (lr 1e-3) on the hypernetwork and the biases over 64
-    parameter samples (32 from each domain of Section 4) sharing the 65536
-    training points; (2) a FastLRNR (r_hat = 32) built from snapshots at
+    """The workflow of Section 3 on the small net: (1) meta phase, 300 Adam
+    steps (lr 1e-3) on the hypernetwork and the biases over 64 parameter
+    samples (32 from each domain of Section 4) sharing the 65536 training
+    points, then 100 steps on all of eq. 3.4 (U and V too, R_orth weight 1e-3)
+    over 16 of them; (2) a FastLRNR (r_hat = 32) built from snapshots at
     f_hyper of 8 of those samples; (3) for every bounded test case of the
     reference leg, s_init = f_hyper(mu) and 200 Adam steps with the LRNR and
     with the FastLRNR gradient, the L1 relative error against the reference
@@ -590,6 +591,26 @@ def run_pipeline(args, torch, api, wl):
             objs.append(float(loss[:, 0].double().mean()) + 1e-3 * float(r[0]))
         api.adam_step(f.theta, mt, vt, g, k)
         api.adam_step(net.b, mb, vb, gb, k)
+    # then all of eq. 3.4 (U and V too, with R_orth) on 16 of the samples
+    mu16 = mu_tr[::4].contiguous()
+    meta_u = api.MetaStep(f, net, mu16, pts)
+    params = [f.theta, net.b, net.U, net.V]
+    mom = [(torch.zeros_like(p), torch.zeros_like(p)) for p in params]
+    for k in range(1, 101):
+        g, gb, loss, r = meta_u(cfg, 1.5, 1e-3, ws=ws)
+        gUs, gVs = [], []
+        for j in range(mu16.shape[0]):
+            gU_j, gV_j = api.basis_grad(net, meta_u.s[j], mu16[j], pts, cfg, ws=ws)
+            gUs.append(gU_j)
+            gVs.append(gV_j)
+        ro, gUo, gVo = api.orth_reg(net)
+        if k in (1, 100):
+            objs.append(float(loss[:, 0].double().mean()) + 1e-3 * float(r[0])
+                        + 1e-3 * float(ro[0]))
+        grads = (g, gb, api.rows_mean(torch.stack(gUs)) + 1e-3 * gUo,
+                 api.rows_mean(torch.stack(gVs)) + 1e-3 * gVo)
+        for p_, (m_, v_), g_ in zip(params, mom, grads):
+            api.adam_step(p_, m_, v_, g_, k)
     torch.cuda.synchronize()
     meta_s = time.time() - t0
     s_snap = api.hyper_forward(f, mu_tr[::8].contiguous())
@@ -642,10 +663,13 @@ def run_pipeline(args, torch, api, wl):
     fast.close()
     init = [c["l1_meta_init"] for c in cases]
     return {
-        "workload": "small net 64 wide x 4 hidden, rank 8, U and V fixed; meta phase 300 steps "
-                    "over 64 samples of the Section 4 domains (Theta and b); FastLRNR r_hat=32 "
+        "workload": "small net 64 wide x 4 hidden, rank 8; meta phase 300 steps over 64 samples "
+                    "of the Section 4 domains (Theta and b), then 100 steps over 16 of them "
+                    "(Theta, b, U, V); FastLRNR r_hat=32 "
                     "from 8 meta samples; 200 fine-tuning steps per bounded test case",
-        "meta_objective_first": objs[0], "meta_objective_last": objs[1], "meta_phase_s": meta_s,
+        "meta_objective_first": objs[0], "meta_objective_theta_b_last": objs[1],
+        "meta_objective_bases_first": objs[2], "meta_objective_bases_last": objs[3],
+        "meta_phase_s": meta_s,
         "l1_meta_init_median": float(np.median(init)),
         "l1_lrnr_final_median": float(np.median([c["lrnr_l1"][-1] for c in cases])),
         "l1_fastlrnr_final_median": float(np.median([c["fastlrnr_l1"][-1] for c in cases])),
