@@ -58,18 +58,19 @@ __device__ inline void point_xt(const KBg& g, int64_t e, float& x, float& t) {
   }
 }
 
-// forward jets; stores W, A and the output jets
+// forward jets; stores W, A and the output jets (RPT >= every rank of the net)
+template <int RPT>
 __global__ void __launch_bounds__(kBgThreads) bg_forward_kernel(KBg g) {
   const int64_t e = (int64_t)blockIdx.x * kBgThreads + threadIdx.x;
   if (e >= g.E) return;
   const KNet& k = g.k;
   float x, t;
   point_xt(g, e, x, t);
-  float y[4][LRNR_MAX_RANK];
+  float y[4][RPT];
   const int r1 = k.r[1];
   const float* V1 = k.V + k.offV[1];
 #pragma unroll
-  for (int j = 0; j < LRNR_MAX_RANK; ++j) {
+  for (int j = 0; j < RPT; ++j) {
     const bool on = j < r1;
     y[0][j] = on ? V1[j] * x + V1[r1 + j] * t : 0.f;
     y[1][j] = on ? V1[j] : 0.f;
@@ -83,7 +84,7 @@ __global__ void __launch_bounds__(kBgThreads) bg_forward_kernel(KBg g) {
     const float* sl = g.s + k.offS[l];
     float* W = g.W[l] + e * 4 * rl;
 #pragma unroll
-    for (int j = 0; j < LRNR_MAX_RANK; ++j)
+    for (int j = 0; j < RPT; ++j)
       if (j < rl) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -94,7 +95,7 @@ __global__ void __launch_bounds__(kBgThreads) bg_forward_kernel(KBg g) {
     if (l == k.L) {   // linear output, M_L = 1
       float u[4] = {b[0], 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int j = 0; j < LRNR_MAX_RANK; ++j)
+      for (int j = 0; j < RPT; ++j)
         if (j < rl)
 #pragma unroll
           for (int c = 0; c < 4; ++c) u[c] = fmaf(U[j], y[c][j], u[c]);
@@ -105,15 +106,15 @@ __global__ void __launch_bounds__(kBgThreads) bg_forward_kernel(KBg g) {
     const int ro = k.r[l + 1];
     const float* V = k.V + k.offV[l + 1];
     float* A = g.A[l] + e * 4 * M;
-    float yn[4][LRNR_MAX_RANK];
+    float yn[4][RPT];
 #pragma unroll
-    for (int j = 0; j < LRNR_MAX_RANK; ++j)
+    for (int j = 0; j < RPT; ++j)
 #pragma unroll
       for (int c = 0; c < 4; ++c) yn[c][j] = 0.f;
     for (int i = 0; i < M; ++i) {
       float a[4] = {b[i], 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int j = 0; j < LRNR_MAX_RANK; ++j)
+      for (int j = 0; j < RPT; ++j)
         if (j < rl)
 #pragma unroll
           for (int c = 0; c < 4; ++c) a[c] = fmaf(U[i * rl + j], y[c][j], a[c]);
@@ -122,13 +123,13 @@ __global__ void __launch_bounds__(kBgThreads) bg_forward_kernel(KBg g) {
       const float sv = sinf(a[0]), cv = cosf(a[0]);
       const float z[4] = {sv, cv * a[1], cv * a[2], cv * a[3] - sv * a[1] * a[1]};
 #pragma unroll
-      for (int j = 0; j < LRNR_MAX_RANK; ++j)
+      for (int j = 0; j < RPT; ++j)
         if (j < ro)
 #pragma unroll
           for (int c = 0; c < 4; ++c) yn[c][j] = fmaf(V[i * ro + j], z[c], yn[c][j]);
     }
 #pragma unroll
-    for (int j = 0; j < LRNR_MAX_RANK; ++j)
+    for (int j = 0; j < RPT; ++j)
 #pragma unroll
       for (int c = 0; c < 4; ++c) y[c][j] = yn[c][j];
   }
@@ -139,6 +140,7 @@ __device__ inline float dphi(float v, int form) {
 }
 
 // output adjoint from the loss, then the reverse jets; stores Abar and Ybar
+template <int RPT>
 __global__ void __launch_bounds__(kBgThreads) bg_reverse_kernel(KBg g) {
   const int64_t e = (int64_t)blockIdx.x * kBgThreads + threadIdx.x;
   if (e >= g.E) return;
@@ -164,7 +166,7 @@ __global__ void __launch_bounds__(kBgThreads) bg_reverse_kernel(KBg g) {
     ub[0] = (j & 1) ? -gb : gb;
   }
   // output layer: abar^L = ubar, wbar = U^L ubar, ybar^L = s^L * wbar
-  float yb[4][LRNR_MAX_RANK];
+  float yb[4][RPT];
   {
     const int L = k.L, rl = k.r[L];
     const float* U = k.U + k.offU[L];
@@ -173,7 +175,7 @@ __global__ void __launch_bounds__(kBgThreads) bg_reverse_kernel(KBg g) {
     for (int c = 0; c < 4; ++c) g.Abar[L][e * 4 + c] = ub[c];
     float* Yb = g.Ybar[L] + e * 4 * rl;
 #pragma unroll
-    for (int j = 0; j < LRNR_MAX_RANK; ++j)
+    for (int j = 0; j < RPT; ++j)
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         yb[c][j] = (j < rl) ? sl[j] * U[j] * ub[c] : 0.f;
@@ -187,15 +189,15 @@ __global__ void __launch_bounds__(kBgThreads) bg_reverse_kernel(KBg g) {
     const float* sl = g.s + k.offS[l];
     const float* A = g.A[l] + e * 4 * M;
     float* Ab = g.Abar[l] + e * 4 * M;
-    float wb[4][LRNR_MAX_RANK];
+    float wb[4][RPT];
 #pragma unroll
-    for (int j = 0; j < LRNR_MAX_RANK; ++j)
+    for (int j = 0; j < RPT; ++j)
 #pragma unroll
       for (int c = 0; c < 4; ++c) wb[c][j] = 0.f;
     for (int i = 0; i < M; ++i) {
       float zb[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int j = 0; j < LRNR_MAX_RANK; ++j)
+      for (int j = 0; j < RPT; ++j)
         if (j < ro)
 #pragma unroll
           for (int c = 0; c < 4; ++c) zb[c] = fmaf(V[i * ro + j], yb[c][j], zb[c]);
@@ -210,14 +212,14 @@ __global__ void __launch_bounds__(kBgThreads) bg_reverse_kernel(KBg g) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) Ab[c * M + i] = ab[c];
 #pragma unroll
-      for (int j = 0; j < LRNR_MAX_RANK; ++j)
+      for (int j = 0; j < RPT; ++j)
         if (j < rl)
 #pragma unroll
           for (int c = 0; c < 4; ++c) wb[c][j] = fmaf(U[i * rl + j], ab[c], wb[c][j]);
     }
     float* Yb = g.Ybar[l] + e * 4 * rl;
 #pragma unroll
-    for (int j = 0; j < LRNR_MAX_RANK; ++j)
+    for (int j = 0; j < RPT; ++j)
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         yb[c][j] = (j < rl) ? sl[j] * wb[c][j] : 0.f;
@@ -381,10 +383,16 @@ int32_t lrnr_basis_grad(const lrnr_net* net, const float* s, const float* mu,
   bg_layout(g.k, g.E, &g, static_cast<float*>(ws));
   if (g.E > 0) {
     const unsigned nb = (unsigned)((g.E + kBgThreads - 1) / kBgThreads);
-    hipLaunchKernelGGL(bg_forward_kernel, dim3(nb), dim3(kBgThreads), 0, st, g);
+    int rmax = 1;
+    for (int l = 1; l <= g.k.L; ++l) rmax = g.k.r[l] > rmax ? g.k.r[l] : rmax;
+    auto fwd = rmax <= 8 ? bg_forward_kernel<8>
+             : rmax <= 16 ? bg_forward_kernel<16> : bg_forward_kernel<LRNR_MAX_RANK>;
+    auto rev = rmax <= 8 ? bg_reverse_kernel<8>
+             : rmax <= 16 ? bg_reverse_kernel<16> : bg_reverse_kernel<LRNR_MAX_RANK>;
+    hipLaunchKernelGGL(fwd, dim3(nb), dim3(kBgThreads), 0, st, g);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "basis gradient forward launch");
-    hipLaunchKernelGGL(bg_reverse_kernel, dim3(nb), dim3(kBgThreads), 0, st, g);
+    hipLaunchKernelGGL(rev, dim3(nb), dim3(kBgThreads), 0, st, g);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "basis gradient reverse launch");
   }

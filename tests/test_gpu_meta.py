@@ -173,10 +173,19 @@ def test_orth_reg_matches_oracle(name, make):
     assert float(v0[0]) < 1e-9
 
 
+def rank16_case():
+    # ranks in (8, 16]: the middle rank tile of the per-point kernels
+    rng = np.random.Generator(np.random.PCG64(17))
+    M = [2, 96, 80, 1]
+    net = wl.make_net(rng, M, wl.ranks(M, 13))
+    return wl.Workload(net, wl.make_points(rng, 700, 90, 70), wl.make_mu(rng, 1))
+
+
 @pytest.mark.parametrize("name,make,form", [("small", lambda: wl.small_lrnr(0, 2048), 0),
                                             ("small_l1", lambda: wl.small_lrnr(0, 1500), 1),
+                                            ("rank13", rank16_case, 0),
                                             ("wide", lambda: wl.big_lrnr(1, 512), 0)],
-                         ids=["small", "small_l1", "wide"])
+                         ids=["small", "small_l1", "rank13", "wide"])
 def test_basis_grad_matches_oracle(name, make, form):
     a = api()
     w = make()
