@@ -25,23 +25,78 @@ def rel_err(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
-def assert_close(got, ref, tol, what=""):
+def _rel_errs(got, ref):
+    """Relative errors of got against ref in the 2-norm and in the max-norm."""
+    re2 = rel_err(got, ref)
+    mref = np.abs(ref).max() if ref.size else 0.0
+    reinf = (np.abs(got - ref).max() / mref) if mref > 0 else (np.abs(got).max() if got.size else 0.0)
+    return re2, reinf
+
+
+# the loss record [total, interior, initial, boundary]: each term on its own
+LOSS_BLOCKS = [1, 1, 1, 1]
+
+
+def s_blocks(net):
+    """Layer blocks of a flat s or grad_s: r_1, ..., r_L."""
+    return [int(x) for x in net.r]
+
+
+def b_blocks(net):
+    """Layer blocks of a flat b or grad_b: M_1, ..., M_L."""
+    return [int(x) for x in net.M[1:]]
+
+
+def u_blocks(net):
+    """Layer blocks of a packed U or grad_U: M_l r_l."""
+    return [int(net.M[l + 1]) * int(net.r[l]) for l in range(len(net.r))]
+
+
+def v_blocks(net):
+    """Layer blocks of a packed V or grad_V: M_{l-1} r_l."""
+    return [int(net.M[l]) * int(net.r[l]) for l in range(len(net.r))]
+
+
+def assert_close(got, ref, tol, what="", blocks=None, block_tol=None):
     """Parity metric: relative error in the 2-norm and in the max-norm,
-    ||got - ref|| <= tol ||ref|| for both.  A per-entry relative test is not
-    used: entries that are the residue of a cancellation (a jet crossing zero
-    at a point, a gradient entry whose per-point terms nearly cancel) carry an
-    FP32 error set by the size of the cancelling terms, which the max-norm
-    bounds."""
+    ||got - ref|| <= tol ||ref|| for both, over the whole vector and, when
+    ``blocks`` (sizes of consecutive blocks, e.g. the layers of grad_s) is
+    given, over every block against that block's own norms (``block_tol``,
+    default tol), so that a layer whose entries are small next to the others
+    is held to the same relative bar.  A per-entry relative test is not used:
+    entries that are the residue of a cancellation (a jet crossing zero at a
+    point, a gradient entry whose per-point terms nearly cancel) carry an FP32
+    error set by the size of the cancelling terms, which the max-norm of the
+    block bounds."""
     got = np.asarray(got, np.float64).reshape(-1)
     ref = np.asarray(ref, np.float64).reshape(-1)
     assert got.shape == ref.shape, (what, got.shape, ref.shape)
     assert np.all(np.isfinite(got)), f"{what}: non-finite output"
-    re2 = rel_err(got, ref)
-    mref = np.abs(ref).max() if ref.size else 0.0
-    reinf = (np.abs(got - ref).max() / mref) if mref > 0 else (np.abs(got).max() if got.size else 0.0)
+    re2, reinf = _rel_errs(got, ref)
     msg = f"{what}: rel err 2-norm {re2:.3e}, max-norm {reinf:.3e} (tol {tol:g})"
-    assert re2 <= tol and reinf <= tol, msg
+    bad = re2 > tol or reinf > tol
+    if blocks is not None:
+        assert sum(blocks) == got.size, (what, blocks, got.size)
+        btol = tol if block_tol is None else block_tol
+        gmax = np.abs(ref).max() if ref.size else 0.0
+        parts, o = [], 0
+        for k, n in enumerate(blocks):
+            g, r = got[o:o + n], ref[o:o + n]
+            o += n
+            if n == 0:
+                continue
+            if np.abs(r).max() == 0.0:
+                # an identically zero block: absolute bar at the global scale
+                e = np.abs(g).max() / gmax if gmax > 0 else np.abs(g).max()
+                parts.append(f"{k + 1}:{e:.1e}(zero)")
+                bad = bad or e > btol
+                continue
+            b2, binf = _rel_errs(g, r)
+            parts.append(f"{k + 1}:{b2:.1e}/{binf:.1e}")
+            bad = bad or b2 > btol or binf > btol
+        msg += f"; per block (2-norm/max-norm, tol {btol:g}) " + " ".join(parts)
     log(f"  {msg}")
+    assert not bad, msg
     return re2
 
 

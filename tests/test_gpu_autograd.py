@@ -10,7 +10,7 @@ import pytest
 import workloads as wl
 from oracle import lrnr_oracle as orc
 
-from _util import assert_close, log
+from _util import assert_close, log, s_blocks
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -65,7 +65,8 @@ def test_cdr_loss_backward_matches_oracle():
         l4, rgs, _ = orc.lrnr_loss(w.net, w.net.split_s(s0[i]), w.mu[i].astype(np.float64),
                                    w.extra["pts"][i], {}, with_grad=True)
         assert_close(lv[i:i + 1], l4[:1], TOL, f"instance {i} loss")
-        assert_close(g[i], float(gout[i]) * rgs, TOL, f"instance {i} d(gout*loss)/ds")
+        assert_close(g[i], float(gout[i]) * rgs, TOL, f"instance {i} d(gout*loss)/ds",
+                     blocks=s_blocks(w.net))
 
 
 def test_cdr_loss_recompute_equals_fused_and_fd():
@@ -118,7 +119,7 @@ def test_lrnr_jets_backward_matches_oracle_vjp_and_fd():
     for i in range(B):
         rgs, _ = orc.lrnr_jets_vjp(w.net, w.net.split_s(s0[i]), xt_h[i].astype(np.float64),
                                    C[i].astype(np.float64))
-        assert_close(g[i], rgs, TOL, f"instance {i} jets VJP")
+        assert_close(g[i], rgs, TOL, f"instance {i} jets VJP", blocks=s_blocks(w.net))
         rj = orc.lrnr_forward_jets(w.net, w.net.split_s(s0[i]), xt_h[i].astype(np.float64))
         assert_close(jets[i, 0].detach().cpu().numpy(), rj[0], TOL, f"instance {i} u")
     # FD along one direction

@@ -9,7 +9,7 @@ import pytest
 import workloads as wl
 from oracle import lrnr_oracle as orc
 
-from _util import assert_close, log
+from _util import assert_close, b_blocks, log, u_blocks, v_blocks
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -142,7 +142,7 @@ def test_meta_step_with_biases_matches_oracle():
     got = float(loss[:, 0].double().mean()) + 0.3 * float(r[0])
     assert abs(got - obj) <= TOL * abs(obj), (got, obj)
     assert_close(g.cpu().numpy(), rg, TOL, "meta step grad theta")
-    assert_close(gb.cpu().numpy(), rgb, TOL, "meta step grad b")
+    assert_close(gb.cpu().numpy(), rgb, TOL, "meta step grad b", blocks=b_blocks(w.net))
     # the mean over samples is a fixed-order sum
     rng = np.random.Generator(np.random.PCG64(2))
     x = rng.standard_normal((37, 1001)).astype(np.float32)
@@ -166,8 +166,10 @@ def test_orth_reg_matches_oracle(name, make):
     v, gU, gV = a.orth_reg(a.DeviceNet.from_net(n2))
     rv, rgU, rgV = orc.orth_reg(n2.U, n2.V, with_grad=True)
     assert abs(float(v[0]) - rv) <= TOL * rv, (float(v[0]), rv)
-    assert_close(gU.cpu().numpy(), np.concatenate([g.ravel() for g in rgU]), TOL, f"{name} grad U")
-    assert_close(gV.cpu().numpy(), np.concatenate([g.ravel() for g in rgV]), TOL, f"{name} grad V")
+    assert_close(gU.cpu().numpy(), np.concatenate([g.ravel() for g in rgU]), TOL, f"{name} grad U",
+                 blocks=u_blocks(n2))
+    assert_close(gV.cpu().numpy(), np.concatenate([g.ravel() for g in rgV]), TOL, f"{name} grad V",
+                 blocks=v_blocks(n2))
     # the generated bases are orthonormal up to FP32 rounding
     v0, _, _ = a.orth_reg(a.DeviceNet.from_net(w.net), with_grad=False)
     assert float(v0[0]) < 1e-9
@@ -200,6 +202,6 @@ def test_basis_grad_matches_oracle(name, make, form):
     torch.cuda.synchronize()
     rU, rV = orc.lrnr_basis_grad(w.net, w.net.s, w.mu[0].astype(np.float64), w.pts,
                                  {"form": form, "w_r": 1.0, "w_0": 0.7, "w_b": 1.3})
-    assert_close(gU.cpu().numpy(), rU, TOL, f"{name} grad U")
-    assert_close(gV.cpu().numpy(), rV, TOL, f"{name} grad V")
+    assert_close(gU.cpu().numpy(), rU, TOL, f"{name} grad U", blocks=u_blocks(w.net))
+    assert_close(gV.cpu().numpy(), rV, TOL, f"{name} grad V", blocks=v_blocks(w.net))
     assert torch.equal(gU, gU2) and torch.equal(gV, gV2)

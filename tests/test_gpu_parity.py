@@ -13,7 +13,7 @@ import pytest
 import workloads as wl
 from oracle import lrnr_oracle as orc
 
-from _util import assert_close, log
+from _util import LOSS_BLOCKS, assert_close, b_blocks, log, s_blocks
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -69,11 +69,12 @@ def check_loss_grad(w, mu_row=0, cfg=None, with_b=True, tag=""):
         ref_cfg["s_ref"] = np.asarray(ref_cfg["s_ref"], np.float32).astype(np.float64)
     l4, rgs, rgb = orc.lrnr_loss(w.net, w.net.s, w.mu[mu_row].astype(np.float64), w.pts,
                                  ref_cfg, with_grad=True)
-    assert_close(loss.cpu().numpy(), l4, TOL, f"{tag} loss")
-    assert_close(loss_only.cpu().numpy(), l4, TOL, f"{tag} loss (loss-only entry)")
-    assert_close(gs.cpu().numpy(), rgs, TOL, f"{tag} grad_s")
+    assert_close(loss.cpu().numpy(), l4, TOL, f"{tag} loss", blocks=LOSS_BLOCKS)
+    assert_close(loss_only.cpu().numpy(), l4, TOL, f"{tag} loss (loss-only entry)",
+                 blocks=LOSS_BLOCKS)
+    assert_close(gs.cpu().numpy(), rgs, TOL, f"{tag} grad_s", blocks=s_blocks(w.net))
     if with_b:
-        assert_close(gb.cpu().numpy(), rgb, TOL, f"{tag} grad_b")
+        assert_close(gb.cpu().numpy(), rgb, TOL, f"{tag} grad_b", blocks=b_blocks(w.net))
     return gs, gb, loss
 
 
@@ -230,9 +231,9 @@ def test_big_net_full_size():
         acc_l += l1.cpu().numpy()
         if k == 3:
             l4, rgs, rgb = orc.lrnr_loss_chunked(w.net, w.net.s, w.mu[0].astype(np.float64), sub, c)
-            assert_close(l1.cpu().numpy(), l4, TOL, "block loss")
-            assert_close(g1.cpu().numpy(), rgs, TOL, "block grad_s")
-            assert_close(b1.cpu().numpy(), rgb, TOL, "block grad_b")
+            assert_close(l1.cpu().numpy(), l4, TOL, "block loss", blocks=LOSS_BLOCKS)
+            assert_close(g1.cpu().numpy(), rgs, TOL, "block grad_s", blocks=s_blocks(w.net))
+            assert_close(b1.cpu().numpy(), rgb, TOL, "block grad_b", blocks=b_blocks(w.net))
     assert_close(gs.cpu().numpy(), acc_s, 1e-5, "full grad_s vs sum of blocks")
     assert_close(gb.cpu().numpy(), acc_b, 1e-5, "full grad_b vs sum of blocks")
     assert_close(loss.cpu().numpy(), acc_l, 1e-5, "full loss vs sum of blocks")
@@ -269,8 +270,8 @@ def test_batched_equals_single_bitwise(width, rank):
     s_list = w.net.split_s(S[2].cpu().numpy())
     l4, rgs, _ = orc.lrnr_loss(w.net, s_list, MU[2].cpu().numpy().astype(np.float64), w.pts, {},
                                with_grad=True)
-    assert_close(gsb[2].cpu().numpy(), rgs, TOL, "batched grad_s")
-    assert_close(lb[2].cpu().numpy(), l4, TOL, "batched loss")
+    assert_close(gsb[2].cpu().numpy(), rgs, TOL, "batched grad_s", blocks=s_blocks(w.net))
+    assert_close(lb[2].cpu().numpy(), l4, TOL, "batched loss", blocks=LOSS_BLOCKS)
 
 
 def test_adam_step_matches_oracle():
@@ -322,8 +323,8 @@ def test_fastlrnr_build_matches_oracle_at_resolved_rank():
     torch.cuda.synchronize()
     l4, rgs = orc.fast_loss(w.net, ref, w.net.s, w.mu[0].astype(np.float64), w.pts, {},
                             with_grad=True)
-    assert_close(loss.cpu().numpy(), l4, TOL, "fast r8 loss")
-    assert_close(gs.cpu().numpy(), rgs, TOL, "fast r8 grad_s")
+    assert_close(loss.cpu().numpy(), l4, TOL, "fast r8 loss", blocks=LOSS_BLOCKS)
+    assert_close(gs.cpu().numpy(), rgs, TOL, "fast r8 grad_s", blocks=s_blocks(w.net))
     jets = a.forward_jets(fast.net, s, pts.xt_r[:512].contiguous()).cpu().numpy()
     rj = orc.fast_forward_jets(w.net, ref, w.net.s, w.pts.xt_r[:512])
     for c, tol in ((0, TOL), (1, TOL), (2, TOL), (3, TOL_XX)):
@@ -364,8 +365,9 @@ def test_fastlrnr_build_from_perturbed_snapshots_matches_oracle():
     torch.cuda.synchronize()
     l4, rgs = orc.fast_loss(w.net, ops, w.net.s, w.mu[0].astype(np.float64), w.pts, {},
                             with_grad=True)
-    assert_close(loss.cpu().numpy(), l4, TOL, "fast r8 (4 snapshot sets) loss")
-    assert_close(gs.cpu().numpy(), rgs, TOL, "fast r8 (4 snapshot sets) grad_s")
+    assert_close(loss.cpu().numpy(), l4, TOL, "fast r8 (4 snapshot sets) loss", blocks=LOSS_BLOCKS)
+    assert_close(gs.cpu().numpy(), rgs, TOL, "fast r8 (4 snapshot sets) grad_s",
+                 blocks=s_blocks(w.net))
     fast.close()
 
 
@@ -404,8 +406,8 @@ def test_fastlrnr_qdeim_matches_oracle(n_sets):
     torch.cuda.synchronize()
     l4, rgs = orc.fast_loss(w.net, ops, w.net.s, w.mu[0].astype(np.float64), w.pts, {},
                             with_grad=True)
-    assert_close(loss.cpu().numpy(), l4, TOL, "fast Q-DEIM r8 loss")
-    assert_close(gs.cpu().numpy(), rgs, TOL, "fast Q-DEIM r8 grad_s")
+    assert_close(loss.cpu().numpy(), l4, TOL, "fast Q-DEIM r8 loss", blocks=LOSS_BLOCKS)
+    assert_close(gs.cpu().numpy(), rgs, TOL, "fast Q-DEIM r8 grad_s", blocks=s_blocks(w.net))
     fast.close()
 
 
@@ -447,8 +449,10 @@ def test_fastlrnr_r32_prefix_operators_and_chain():
     torch.cuda.synchronize()
     l4, rgs = orc.fast_loss(w.net, ops, w.net.s, w.mu[0].astype(np.float64), w.pts, {},
                             with_grad=True)
-    assert_close(loss.cpu().numpy(), l4, TOL, "fast r32 loss (device operators)")
-    assert_close(gs.cpu().numpy(), rgs, TOL, "fast r32 grad_s (device operators)")
+    assert_close(loss.cpu().numpy(), l4, TOL, "fast r32 loss (device operators)",
+                 blocks=LOSS_BLOCKS)
+    assert_close(gs.cpu().numpy(), rgs, TOL, "fast r32 grad_s (device operators)",
+                 blocks=s_blocks(w.net))
     fast.close()
 
 
@@ -464,6 +468,7 @@ def test_fastlrnr_full_index_set_equals_lrnr():
     gf, lf = fast.grad_s(s, mu, pts, a.LossCfg())
     gl, _, ll = a.grad_s(net, s, mu, pts, a.LossCfg(), with_b=False)
     torch.cuda.synchronize()
-    assert_close(gf.cpu().numpy(), gl.cpu().numpy(), TOL, "full-set fast vs lrnr grad_s")
+    assert_close(gf.cpu().numpy(), gl.cpu().numpy(), TOL, "full-set fast vs lrnr grad_s",
+                 blocks=s_blocks(w.net))
     assert_close(lf.cpu().numpy(), ll.cpu().numpy(), TOL, "full-set fast vs lrnr loss")
     fast.close()

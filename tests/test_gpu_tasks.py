@@ -12,7 +12,7 @@ import pytest
 import workloads as wl
 from oracle import lrnr_oracle as orc
 
-from _util import assert_close, log
+from _util import LOSS_BLOCKS, assert_close, b_blocks, log, s_blocks
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -117,9 +117,9 @@ def test_tasks_grad_loss_vs_oracle_and_single_path(kind):
         gs, gb, loss = it.outputs()
         l4, rgs, rgb = orc.lrnr_loss(it.net, it.s_list(), it.mu.astype(np.float64), it.pts, {},
                                      with_grad=True)
-        assert_close(loss, l4, TOL, f"task {i} loss")
-        assert_close(gs, rgs, TOL, f"task {i} grad_s")
-        assert_close(gb, rgb, TOL, f"task {i} grad_b")
+        assert_close(loss, l4, TOL, f"task {i} loss", blocks=LOSS_BLOCKS)
+        assert_close(gs, rgs, TOL, f"task {i} grad_s", blocks=s_blocks(it.net))
+        assert_close(gb, rgb, TOL, f"task {i} grad_b", blocks=b_blocks(it.net))
         # the single-instance entry point on the same data
         pts = a.DevicePoints(it.pts.xt_r, it.pts.x_0, it.pts.t_b)
         sgs, sgb, sl = a.grad_s(dn[it.net_id], it.s, it.mu_d, pts, cfg)
@@ -193,8 +193,8 @@ def test_tasks_jets_value_vjp_vs_oracle(kind):
             assert_close(j[c], rj[c], tol, f"task {i} jets[{c}]")
         assert_close(it.val.cpu().numpy(), rj[0], TOL, f"task {i} value")
         rgs, rgb = orc.lrnr_jets_vjp(it.net, it.s_list(), xt, it.cot_host.astype(np.float64))
-        assert_close(it.gs.cpu().numpy(), rgs, TOL, f"task {i} vjp grad_s")
-        assert_close(it.gb.cpu().numpy(), rgb, TOL, f"task {i} vjp grad_b")
+        assert_close(it.gs.cpu().numpy(), rgs, TOL, f"task {i} vjp grad_s", blocks=s_blocks(it.net))
+        assert_close(it.gb.cpu().numpy(), rgb, TOL, f"task {i} vjp grad_b", blocks=b_blocks(it.net))
         # the single-instance jets entry point
         sj = a.forward_jets(dn[it.net_id], it.s, it.xt).cpu().numpy()
         assert_close(j, sj, 1e-6, f"task {i} jets vs lrnr_forward_jets")
@@ -223,8 +223,8 @@ def test_tasks_empty_and_many(kind):
         if i % 10 == 0:
             l4, rgs, rgb = orc.lrnr_loss(it.net, it.s_list(), it.mu.astype(np.float64), it.pts,
                                          {}, with_grad=True)
-            assert_close(loss, l4, TOL, f"task {i} loss")
-            assert_close(gs, rgs, TOL, f"task {i} grad_s")
+            assert_close(loss, l4, TOL, f"task {i} loss", blocks=LOSS_BLOCKS)
+            assert_close(gs, rgs, TOL, f"task {i} grad_s", blocks=s_blocks(it.net))
         assert np.all(np.isfinite(gs)) and np.all(np.isfinite(loss)), i
 
 
