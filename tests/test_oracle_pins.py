@@ -591,3 +591,86 @@ def test_basis_grad_complex_step():
 
         c = _complex_step_grad(f, np.concatenate([m.ravel() for m in mats]).astype(np.float64))
         np.testing.assert_allclose(g, c, rtol=1e-10, atol=1e-13)
+
+
+# ------------------------------------------- snapshot states and POD basis --
+
+def _torch_hidden(net, s_list, xt, drop_bias=None):
+    """Hidden states of eq. 2.1 with W^l = U^l diag(s^l) V^lT (eq. 2.2) in
+    PyTorch float64; drop_bias = l leaves out b^l (a planted mistake)."""
+    torch = pytest.importorskip("torch")
+    dt = torch.float64
+    z = torch.tensor(np.asarray(xt, np.float64), dtype=dt)
+    out = []
+    for l in range(net.L - 1):
+        W = (torch.tensor(net.U[l], dtype=dt) @ torch.diag(torch.tensor(s_list[l], dtype=dt))
+             @ torch.tensor(net.V[l], dtype=dt).T)
+        a = torch.nn.functional.linear(z, W)
+        if l != drop_bias:
+            a = a + torch.tensor(net.b[l], dtype=dt)
+        z = torch.sin(a)
+        out.append(z.numpy())
+    return out
+
+
+def test_hidden_values_match_torch_textbook_mlp():
+    """lrnr_hidden_values (the snapshot states of eq. 2.7) against PyTorch's
+    float64 forward of the textbook network, at s and at a perturbed s; the
+    comparison separates the oracle from the same forward with any one bias
+    left out, so a dropped or misplaced bias fails it."""
+    net, pts, _ = tiny_case(seed=13)
+    rng = np.random.default_rng(3)
+    for s_list in (net.s, [x * (1 + 0.2 * rng.standard_normal(x.shape)) for x in net.s]):
+        Z = orc.lrnr_hidden_values(net, s_list, pts.xt_r)
+        T = _torch_hidden(net, s_list, pts.xt_r)
+        assert len(Z) == net.L - 1
+        for z, t in zip(Z, T):
+            np.testing.assert_allclose(z, t, rtol=0, atol=1e-13)
+        for l in range(net.L - 1):
+            Tb = _torch_hidden(net, s_list, pts.xt_r, drop_bias=l)
+            assert max(np.abs(z - t).max() for z, t in zip(Z, Tb)) > 1e-3, l
+
+
+def test_hidden_values_feed_the_output_layer():
+    """The last hidden state through the linear output layer of eq. 2.1 is
+    the u of the forward jets (which the autograd and complex-step pins fix)."""
+    net, pts, _ = tiny_case(seed=14)
+    z = orc.lrnr_hidden_values(net, net.s, pts.xt_r)[-1]
+    L = net.L
+    W = (net.U[L - 1].astype(np.float64) * net.s[L - 1].astype(np.float64)) @ \
+        net.V[L - 1].astype(np.float64).T
+    u = z @ W.T + net.b[L - 1].astype(np.float64)
+    np.testing.assert_allclose(u[:, 0], orc.lrnr_forward_jets(net, net.s, pts.xt_r)[0],
+                               rtol=0, atol=1e-13)
+
+
+def test_pod_basis_is_the_leading_singular_subspace_in_order():
+    """Eckart-Young: the projection on the leading r_hat left singular
+    vectors leaves exactly the trailing singular values, ||Z - Xi Xi^T Z||_F^2
+    = sum_{j > r_hat} sigma_j^2, and column j alone carries sigma_j
+    (||xi_j^T Z|| = sigma_j, descending), with the singular values from
+    scipy's svdvals.  Trailing or reordered vectors fail both checks."""
+    from scipy.linalg import svdvals
+    rng = np.random.default_rng(21)
+    # distinct, decaying singular values (as the snapshot matrices have)
+    A = np.linalg.qr(rng.standard_normal((40, 40)))[0]
+    B = np.linalg.qr(rng.standard_normal((300, 40)))[0]
+    Z = (A * np.geomspace(10.0, 1e-3, 40)) @ B.T
+    Z += 1e-6 * rng.standard_normal(Z.shape)
+    sv = svdvals(Z)
+
+    def check(Xi, r):
+        res = np.linalg.norm(Z - Xi @ (Xi.T @ Z)) ** 2
+        ok_tail = abs(res - np.sum(sv[r:] ** 2)) <= 1e-9 * np.sum(sv ** 2)
+        ok_cols = np.allclose(np.linalg.norm(Xi.T @ Z, axis=1), sv[:r], rtol=1e-9)
+        return ok_tail and ok_cols
+
+    for r in (1, 5, 16, 40):
+        Xi = orc.pod_basis(Z, r)
+        assert Xi.shape == (40, r)
+        np.testing.assert_allclose(Xi.T @ Xi, np.eye(r), atol=1e-12)
+        assert check(Xi, r), r
+    # planted mistakes: trailing singular vectors, or the leading ones out of order
+    u = np.linalg.svd(Z, full_matrices=False)[0]
+    assert not check(u[:, -8:], 8)
+    assert not check(u[:, [1, 0, 2, 3, 4, 5, 6, 7]], 8)
