@@ -49,7 +49,9 @@ enum {
 /*
  * An LRNR with frozen bases (eq. 2.4).  L weight layers, widths M[0..L] with
  * M[0] = 2 (input (x, t)) and M[L] = 1 (scalar u); ranks r[1..L] (r[0] unused)
- * with 1 <= r[l] <= min(M[l-1], M[l], LRNR_MAX_RANK).  Layer l computes
+ * with 1 <= r[l] <= LRNR_MAX_RANK, r[1] <= M[0] and r[L] <= M[L].  A hidden
+ * rank may exceed the widths next to it: the reduced net of a FastLRNR has
+ * widths r_hat_l that may lie below r_l (eq. 2.7-2.8).  Layer l computes
  * z^l = sin(U^l diag(s^l) V^lT z^{l-1} + b^l) for l < L and the linear
  * u = U^L diag(s^L) V^LT z^{L-1} + b^L (eq. 2.1 with eq. 2.2).
  *  U [dev]: U^1..U^L concatenated, U^l row-major [M[l]][r[l]].
@@ -346,7 +348,9 @@ int32_t lrnr_srv_destroy(lrnr_srv* srv);
  *  s_snap  [dev]  [n_s][r_total]
  *  xt_snap [dev]  [n_snap][2]
  *  r_hat   [host] [L-1] reduced widths of hidden layers 1..L-1, each in
- *                 [1, min(M[l], n_s * n_snap, LRNR_MAX_WIDTH)]
+ *                 [1, min(M[l], n_s * n_snap, LRNR_MAX_WIDTH)]; a width
+ *                 below the layer's rank r_l is allowed (Section 4 uses
+ *                 r_hat well below r)
  *  out     [host] receives the handle; free it with fastlrnr_destroy.
  * Synchronises the stream (the selection runs on the device but its result
  * sizes the handle).  The net's device arrays are not referenced afterwards.

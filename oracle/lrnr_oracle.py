@@ -34,6 +34,7 @@ of eq. 2.8.  With the full index set the two must agree, which pins both.
 """
 from __future__ import annotations
 
+import contextlib
 import math
 
 import numpy as np
@@ -42,12 +43,30 @@ TWO_PI = 2.0 * math.pi
 JETS = ("v", "x", "t", "xx")
 
 
+# Real type of the oracle's arithmetic: float64.  ``working_precision`` can
+# switch it for a test that needs the rounding floor of the same chain in
+# float32 (how far an FP32 evaluation of these formulas lands from the
+# float64 one); the oracle proper never runs in anything but float64.
+_REAL = np.float64
+
+
+@contextlib.contextmanager
+def working_precision(dtype):
+    """Run the oracle's real arithmetic in ``dtype`` inside the block."""
+    global _REAL
+    old, _REAL = _REAL, np.dtype(dtype).type
+    try:
+        yield
+    finally:
+        _REAL = old
+
+
 def _f(a):
     """Upcast an FP32 input to float64 (complex inputs stay complex)."""
     a = np.asarray(a)
     if np.iscomplexobj(a):
         return a.astype(np.complex128)
-    return a.astype(np.float64)
+    return a.astype(_REAL)
 
 
 def _sgn(x):
@@ -196,7 +215,7 @@ def _loss_and_ubar(jets, n_r, n_0, n_b, x0, mu, cfg):
         w_b / max(n_b, 1) * _phi(eb, form).sum() if n_b else 0.0,
     ]
     n_all = u.shape[0]
-    dt = np.result_type(u, np.float64)
+    dt = np.result_type(u, _REAL)
     ubar = {c: np.zeros(n_all, dt) for c in JETS}
     if n_r:
         g = w_r / n_r * _dphi(res, form)

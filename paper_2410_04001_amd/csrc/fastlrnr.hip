@@ -448,7 +448,7 @@ int32_t build(const lrnr_net* net, const float* s_snap, int32_t n_s, const float
   for (int l = 1; l <= L; ++l) {
     const int rl = net->r[l];
     if (l < L && (net->M[l] < 1 || net->M[l] > LRNR_MAX_WIDTH)) return LRNR_EUNSUPPORTED;
-    if (rl < 1 || rl > net->M[l] || rl > net->M[l - 1]) return LRNR_EINVAL;
+    if (rl < 1 || (l == 1 && rl > net->M[0]) || (l == L && rl > net->M[L])) return LRNR_EINVAL;
     if (rl > LRNR_MAX_RANK) return LRNR_EUNSUPPORTED;
     k.r[l] = rl;
     k.offU[l] = oU;

@@ -53,8 +53,14 @@ int32_t make_knet(const lrnr_net* net, KNet* k, int* RP, int* Wmax_p) {
     if (l < L && (Ml < 1 || Ml > LRNR_MAX_WIDTH))
       return fail(Ml > LRNR_MAX_WIDTH ? LRNR_EUNSUPPORTED : LRNR_EINVAL,
                   "M[%d]=%d outside [1,%d]", l, Ml, LRNR_MAX_WIDTH);
-    if (rl < 1 || rl > Ml || rl > Mp)
-      return fail(LRNR_EINVAL, "r[%d]=%d outside [1, min(M[%d], M[%d])]", l, rl, l - 1, l);
+    // The input layer's rank is bounded by (x, t) and the output layer's by
+    // the scalar u; a hidden rank may exceed the widths next to it (the
+    // reduced net of a FastLRNR has widths r_hat_l that may be below r_l,
+    // eq. 2.7-2.8: U_hat^l is r_hat_l x r_l): rank and width are padded
+    // independently in the kernels.
+    if (rl < 1 || (l == 1 && rl > Mp) || (l == L && rl > Ml))
+      return fail(LRNR_EINVAL, "r[%d]=%d outside [1, %s]", l, rl,
+                  l == 1 ? "M[0]" : l == L ? "M[L]" : "LRNR_MAX_RANK");
     if (rl > LRNR_MAX_RANK)
       return fail(LRNR_EUNSUPPORTED, "r[%d]=%d above %d", l, rl, LRNR_MAX_RANK);
     k->r[l] = rl;

@@ -57,7 +57,20 @@ def v_blocks(net):
     return [int(net.M[l]) * int(net.r[l]) for l in range(len(net.r))]
 
 
-def assert_close(got, ref, tol, what="", blocks=None, block_tol=None):
+# A block whose FP32 value is the residue of a cancellation (a boundary-only
+# loss term of two nearly equal values of u, a gradient entry whose per-point
+# terms cancel, an entry that is exactly zero in exact arithmetic) cannot meet
+# a relative bar against its own norm in any FP32 evaluation.  Such a block is
+# held instead to FLOOR_FACTOR times the error of the oracle's own chain run
+# in float32 on the same inputs (the rounding floor of the formulas, measured,
+# not assumed).  The factor allows for a different FP32 evaluation: the kernels
+# take sin/cos from the hardware units (absolute error up to 4.3e-7 against
+# the correctly rounded 6e-8 of numpy) and sum in another order; measured
+# kernel-to-floor ratios on the cases where the floor binds are up to ~5.
+FLOOR_FACTOR = 10.0
+
+
+def assert_close(got, ref, tol, what="", blocks=None, block_tol=None, floor=None):
     """Parity metric: relative error in the 2-norm and in the max-norm,
     ||got - ref|| <= tol ||ref|| for both, over the whole vector and, when
     ``blocks`` (sizes of consecutive blocks, e.g. the layers of grad_s) is
@@ -67,7 +80,12 @@ def assert_close(got, ref, tol, what="", blocks=None, block_tol=None):
     entries that are the residue of a cancellation (a jet crossing zero at a
     point, a gradient entry whose per-point terms nearly cancel) carry an FP32
     error set by the size of the cancelling terms, which the max-norm of the
-    block bounds."""
+    block bounds.
+
+    ``floor``: a callable returning the same quantity from the oracle run in
+    float32 (``oracle.lrnr_oracle.working_precision``).  It is evaluated only
+    when a block misses its bar; that block then passes if its errors stay
+    within FLOOR_FACTOR times the float32 oracle's errors on the block."""
     got = np.asarray(got, np.float64).reshape(-1)
     ref = np.asarray(ref, np.float64).reshape(-1)
     assert got.shape == ref.shape, (what, got.shape, ref.shape)
@@ -79,6 +97,7 @@ def assert_close(got, ref, tol, what="", blocks=None, block_tol=None):
         assert sum(blocks) == got.size, (what, blocks, got.size)
         btol = tol if block_tol is None else block_tol
         gmax = np.abs(ref).max() if ref.size else 0.0
+        ref32 = None
         parts, o = [], 0
         for k, n in enumerate(blocks):
             g, r = got[o:o + n], ref[o:o + n]
@@ -92,12 +111,37 @@ def assert_close(got, ref, tol, what="", blocks=None, block_tol=None):
                 bad = bad or e > btol
                 continue
             b2, binf = _rel_errs(g, r)
-            parts.append(f"{k + 1}:{b2:.1e}/{binf:.1e}")
-            bad = bad or b2 > btol or binf > btol
+            part = f"{k + 1}:{b2:.1e}/{binf:.1e}"
+            if (b2 > btol or binf > btol) and floor is not None:
+                if ref32 is None:
+                    ref32 = np.asarray(floor(), np.float64).reshape(-1)
+                    assert ref32.shape == ref.shape, (what, ref32.shape, ref.shape)
+                f2, finf = _rel_errs(ref32[o - n:o], r)
+                lim2, liminf = max(btol, FLOOR_FACTOR * f2), max(btol, FLOOR_FACTOR * finf)
+                part += f"(fp32 floor {f2:.1e}/{finf:.1e})"
+                bad = bad or b2 > lim2 or binf > liminf
+            else:
+                bad = bad or b2 > btol or binf > btol
+            parts.append(part)
         msg += f"; per block (2-norm/max-norm, tol {btol:g}) " + " ".join(parts)
     log(f"  {msg}")
     assert not bad, msg
     return re2
+
+
+def fp32(fn):
+    """A memoised zero-argument callable: the oracle call ``fn`` (no
+    arguments) run with the oracle's arithmetic in float32, for the
+    ``floor`` of assert_close."""
+    box = []
+
+    def run():
+        if not box:
+            from oracle import lrnr_oracle as orc
+            with orc.working_precision(np.float32):
+                box.append(fn())
+        return box[0]
+    return run
 
 
 def log(*a):

@@ -66,6 +66,11 @@ def test_workspace_size_and_validation(lib):
     assert lib.lrnr_workspace_size(C.byref(good), C.byref(_pts(n_r=-1)), 1) == 0
     assert lib.lrnr_workspace_size(C.byref(good), C.byref(_pts(ptr=0)), 1) == 0
     assert lib.lrnr_workspace_size(C.byref(good), C.byref(pts), 0) == 0
+    # a hidden rank above the widths next to it is valid: the reduced net of a
+    # FastLRNR has widths r_hat_l that may be below the ranks (eq. 2.7-2.8)
+    narrow = _net(M=(2, 4, 4, 5, 4, 1), r=(0, 2, 8, 20, 8, 1))
+    assert lib.lrnr_workspace_size(C.byref(narrow), C.byref(pts), 1) > 0
+    assert lib.lrnr_workspace_size(C.byref(_net(M=(2, 1, 1, 1, 1, 1))), C.byref(pts), 1) > 0
     # empty point sets are valid and still need a (minimal) workspace
     assert lib.lrnr_workspace_size(C.byref(good), C.byref(_pts(0, 0, 0, ptr=0)), 1) >= 256
 

@@ -12,7 +12,7 @@ import pytest
 import workloads as wl
 from oracle import lrnr_oracle as orc
 
-from _util import LOSS_BLOCKS, assert_close, log, s_blocks
+from _util import LOSS_BLOCKS, assert_close, fp32, log, s_blocks
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -79,9 +79,14 @@ def test_lrnr_factored_bias_matches_oracle(name, make, q, zero):
     np.testing.assert_allclose(b.cpu().numpy(), b_ref, rtol=1e-6, atol=1e-7)
     l4, rgs, rgsb = orc.lrnr_loss_factored_bias(w.net, w.net.s, B, sb,
                                                 w.mu[0].astype(np.float64), w.pts, {}, True)
-    assert_close(loss.cpu().numpy(), l4, TOL, f"{name} loss", blocks=LOSS_BLOCKS)
-    assert_close(gs.cpu().numpy(), rgs, TOL, f"{name} grad_s", blocks=s_blocks(w.net))
-    assert_close(gsb.cpu().numpy(), rgsb, TOL, f"{name} grad_sb", blocks=[b.shape[1] for b in B])
+    f32 = fp32(lambda: orc.lrnr_loss_factored_bias(w.net, w.net.s, B, sb, w.mu[0], w.pts, {},
+                                                   True))
+    assert_close(loss.cpu().numpy(), l4, TOL, f"{name} loss", blocks=LOSS_BLOCKS,
+                 floor=lambda: f32()[0])
+    assert_close(gs.cpu().numpy(), rgs, TOL, f"{name} grad_s", blocks=s_blocks(w.net),
+                 floor=lambda: f32()[1])
+    assert_close(gsb.cpu().numpy(), rgsb, TOL, f"{name} grad_sb", blocks=[b.shape[1] for b in B],
+                 floor=lambda: f32()[2])
 
 
 def test_bias_grad_is_the_transposed_basis_product():

@@ -13,7 +13,7 @@ import pytest
 import workloads as wl
 from oracle import lrnr_oracle as orc
 
-from _util import LOSS_BLOCKS, assert_close, b_blocks, log, s_blocks
+from _util import LOSS_BLOCKS, assert_close, b_blocks, fp32, log, s_blocks
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -69,12 +69,17 @@ def check_loss_grad(w, mu_row=0, cfg=None, with_b=True, tag=""):
         ref_cfg["s_ref"] = np.asarray(ref_cfg["s_ref"], np.float32).astype(np.float64)
     l4, rgs, rgb = orc.lrnr_loss(w.net, w.net.s, w.mu[mu_row].astype(np.float64), w.pts,
                                  ref_cfg, with_grad=True)
-    assert_close(loss.cpu().numpy(), l4, TOL, f"{tag} loss", blocks=LOSS_BLOCKS)
+    f32 = fp32(lambda: orc.lrnr_loss(w.net, w.net.s, w.mu[mu_row], w.pts, ref_cfg,
+                                     with_grad=True))
+    assert_close(loss.cpu().numpy(), l4, TOL, f"{tag} loss", blocks=LOSS_BLOCKS,
+                 floor=lambda: f32()[0])
     assert_close(loss_only.cpu().numpy(), l4, TOL, f"{tag} loss (loss-only entry)",
-                 blocks=LOSS_BLOCKS)
-    assert_close(gs.cpu().numpy(), rgs, TOL, f"{tag} grad_s", blocks=s_blocks(w.net))
+                 blocks=LOSS_BLOCKS, floor=lambda: f32()[0])
+    assert_close(gs.cpu().numpy(), rgs, TOL, f"{tag} grad_s", blocks=s_blocks(w.net),
+                 floor=lambda: f32()[1])
     if with_b:
-        assert_close(gb.cpu().numpy(), rgb, TOL, f"{tag} grad_b", blocks=b_blocks(w.net))
+        assert_close(gb.cpu().numpy(), rgb, TOL, f"{tag} grad_b", blocks=b_blocks(w.net),
+                     floor=lambda: f32()[2])
     return gs, gb, loss
 
 
@@ -471,4 +476,46 @@ def test_fastlrnr_full_index_set_equals_lrnr():
     assert_close(gf.cpu().numpy(), gl.cpu().numpy(), TOL, "full-set fast vs lrnr grad_s",
                  blocks=s_blocks(w.net))
     assert_close(lf.cpu().numpy(), ll.cpu().numpy(), TOL, "full-set fast vs lrnr loss")
+    fast.close()
+
+
+@pytest.mark.parametrize("which,r_hat", [("small", 4), ("wide", 5)])
+def test_fastlrnr_reduced_width_below_rank(which, r_hat):
+    """The paper's own regime (Section 2.2 eq. 2.6-2.8, Section 4): reduced
+    widths r_hat_l below the ranks r_l, so U_hat^l = P^T U^l is r_hat x r and
+    V_hat^{l+1} is r_hat x r_{l+1}.  At r_hat = 4 on the rank-8 net and
+    r_hat = 5 on the rank-20 working-size net (both inside the resolved
+    snapshot spectrum) the device picks the oracle's indices, and the FastLRNR
+    loss, gradient and jets match the oracle's eq. 2.8 chain."""
+    a = api()
+    if which == "small":
+        w = wl.fast_case(2, n=8192)
+        xs = w.extra["xt_snap"]
+    else:
+        w = wl.big_lrnr(1, 8192)
+        xs = wl.uniform_points(np.random.Generator(np.random.PCG64(2)), 2048)
+    k = resolved_modes(w.net, xs)
+    log(f"[case] fastlrnr {which} r_hat={r_hat} < r={max(w.net.r)}, resolved modes {k}")
+    assert min(k) >= r_hat
+    net, s, pts, mu = to_dev(w)
+    fast = a.FastLRNR(net, s.reshape(1, -1), torch.tensor(xs, device="cuda"), r_hat)
+    P = fast.indices()
+    ref = orc.fastlrnr_build(w.net, [w.net.s], xs, r_hat)
+    for p, q in zip(P, ref["P"]):
+        assert np.array_equal(p, q), (p, q)
+    ops = fast.operators()
+    for l in range(len(P)):
+        assert ops["U_hat"][l].shape == (r_hat, w.net.r[l])
+        assert ops["V_hat"][l].shape == (r_hat, w.net.r[l + 1])
+    gs, loss = fast.grad_s(s, mu, pts, a.LossCfg())
+    torch.cuda.synchronize()
+    l4, rgs = orc.fast_loss(w.net, ref, w.net.s, w.mu[0].astype(np.float64), w.pts, {},
+                            with_grad=True)
+    tag = f"fast {which} r_hat={r_hat}"
+    assert_close(loss.cpu().numpy(), l4, TOL, f"{tag} loss", blocks=LOSS_BLOCKS)
+    assert_close(gs.cpu().numpy(), rgs, TOL, f"{tag} grad_s", blocks=s_blocks(w.net))
+    jets = a.forward_jets(fast.net, s, pts.xt_r[:512].contiguous()).cpu().numpy()
+    rj = orc.fast_forward_jets(w.net, ref, w.net.s, w.pts.xt_r[:512])
+    for c, tol in ((0, TOL), (1, TOL), (2, TOL), (3, TOL_XX)):
+        assert_close(jets[c], rj[c], tol, f"{tag} jets[{c}]")
     fast.close()
