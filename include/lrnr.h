@@ -162,6 +162,27 @@ int32_t lrnr_grad_s(const lrnr_net* net, const float* s, const float* mu,
                     void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * lrnr_grad_s for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation, kernels and results (bitwise) as lrnr_grad_s, with the
+ * workspace taken from a fixed device array inside the library instead of a
+ * caller buffer.  The array holds LRNR_NOALLOC_SCRATCH_BYTES per GPU, set up
+ * on the first call on each device and held until the process ends; nothing
+ * is allocated or freed on any call.  Sizes whose lrnr_workspace_size exceeds
+ * it return LRNR_EUNSUPPORTED before any device work (64 MiB holds the
+ * 64-wide rank-8 net up to about 90,000 interior points with N/8 initial and
+ * N/8 boundary points, the 256-wide rank-20 net up to about 30,000).  Every
+ * call on one GPU shares that GPU's array and leaves its contents behind (no
+ * part of it needs to start at zero): calls that overlap on one GPU (other
+ * streams or threads) race and must be serialised by the caller.  Other
+ * arguments as lrnr_grad_s.
+ */
+#define LRNR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int32_t lrnr_grad_s_noalloc(const lrnr_net* net, const float* s, const float* mu,
+                            const lrnr_points* pts, const lrnr_loss_cfg* cfg,
+                            float* grad_s, float* grad_b, float* loss, void* stream);
+
+/*
  * Batched loss + gradient for B instances that share the net and the point
  * set but have their own coefficients and PDE parameters:
  *  s      [dev] [B][r_total]

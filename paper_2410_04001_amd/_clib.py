@@ -136,6 +136,7 @@ SIGNATURES = {
     "lrnr_residual_loss": (I32, [NETP, P, P, PTSP, CFGP, P, P, SZ, P]),
     "lrnr_grad_s": (I32, [NETP, P, P, PTSP, CFGP, P, P, P, P, SZ, P]),
     "lrnr_grad_s_batched": (I32, [NETP, I32, P, P, PTSP, CFGP, P, P, P, SZ, P]),
+    "lrnr_grad_s_noalloc": (I32, [NETP, P, P, PTSP, CFGP, P, P, P, P]),
     "lrnr_tasks_workspace_size": (SZ, [I32, NETP, I32, TASKP, I32]),
     "lrnr_tasks_run": (I32, [I32, NETP, I32, TASKP, I32, CFGP, P, SZ, P]),
     "lrnr_srv_clock": (C.c_double, []),

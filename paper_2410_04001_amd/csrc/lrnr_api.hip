@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <mutex>
 #include <string>
 
 #include "lrnr_internal.h"
@@ -14,6 +15,19 @@ using namespace lrnr;
 namespace {
 thread_local std::string g_detail;
 thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+}  // namespace
+
+// Workspace of lrnr_grad_s_noalloc: one fixed device array per GPU, held
+// until the process ends.  Host code never uses the array's name as an
+// address; it takes each device's address once (hipGetSymbolAddress, with
+// that device current) and passes that pointer to the kernels.
+constexpr size_t kScratchBytes = LRNR_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
 }  // namespace
 
 namespace lrnr {
@@ -286,6 +300,39 @@ int32_t lrnr_grad_s_batched(const lrnr_net* net, int32_t B, const float* s, cons
                             const lrnr_points* pts, const lrnr_loss_cfg* cfg, float* grad_s,
                             float* loss, void* ws, size_t ws_bytes, void* stream) {
   return run_loss(net, B, s, mu, pts, cfg, grad_s, nullptr, loss, ws, ws_bytes, stream, true);
+}
+
+int32_t lrnr_grad_s_noalloc(const lrnr_net* net, const float* s, const float* mu,
+                            const lrnr_points* pts, const lrnr_loss_cfg* cfg, float* grad_s,
+                            float* grad_b, float* loss, void* stream) {
+  // sizes beyond the fixed scratch are refused before any device work (an
+  // invalid net or point set gives 0 here and is reported by run_loss)
+  const size_t need = lrnr_workspace_size(net, pts, 1);
+  if (need > kScratchBytes)
+    return fail(LRNR_EUNSUPPORTED, "needs %zu bytes of workspace, the fixed scratch holds %zu",
+                need, kScratchBytes);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kScratchDevices)
+    return fail(LRNR_EUNSUPPORTED, "device %d beyond the %d the scratch table covers", dev,
+                kScratchDevices);
+  void* ws = nullptr;
+  {
+    // set-up, once per device with that device current: the array's address
+    // on this GPU (each GPU holds its own copy at its own address)
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* ptr = nullptr;
+      e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+      if (!ptr) return fail(LRNR_EHIP, "scratch has no device address");
+      g_scratch_ptr[dev] = ptr;
+    }
+    ws = g_scratch_ptr[dev];
+  }
+  return run_loss(net, 1, s, mu, pts, cfg, grad_s, grad_b, loss, ws, kScratchBytes, stream,
+                  true);
 }
 
 int32_t lrnr_adam_step(float* s, float* m, float* v, const float* g, int64_t n, int32_t step,

@@ -118,6 +118,13 @@ def test_entry_points_reject_bad_arguments_without_device_work(lib):
     assert lib.fastlrnr_grad_s(None, out, out, C.byref(pts), C.byref(cfg), out, out, out,
                                1 << 30, None) == cl.EINVAL
     assert lib.fastlrnr_destroy(None) == cl.EINVAL
+    # the workspace-free gradient refuses sizes beyond its fixed scratch
+    # before any device work
+    n = 1 << 20
+    big = _pts(n, n // 8, n // 8)
+    assert lib.lrnr_workspace_size(C.byref(net), C.byref(big), 1) > 64 << 20
+    assert lib.lrnr_grad_s_noalloc(C.byref(net), out, out, C.byref(big), C.byref(cfg), out, out,
+                                   out, None) == cl.EUNSUPPORTED
 
 
 def test_status_strings(lib):
