@@ -27,6 +27,8 @@ Paper passages followed (arXiv 2410.04001):
   * Section 2.1 (remark on the biases): factored biases b^l = B^l s_b^l.
   * Section 3.1, eq. (3.1)-(3.4): hypernetwork s = f_hyper(mu; Theta), meta
     loss over parameter samples, R_sparse (bases held fixed).
+  * Section 4 (meta-learning run): truncation of the coefficients that the
+    hypernetwork sets to zero, with the matching columns of U and V.
 
 The two networks are computed by two different routes on purpose: LRNR by the
 dense route (form W^l explicitly, run eq. 2.1), FastLRNR by the reduced chain
@@ -633,6 +635,37 @@ def hyper_backward(H, cache, s_bar):
         grads[k] = (g.T @ h_in, g.sum(axis=0))
         g = g @ W
     return np.concatenate([np.concatenate([gW.ravel(), gc]) for gW, gc in grads])
+
+
+def truncate(net, H, theta, mus):
+    """Truncation after meta-learning (Section 4): a coefficient s^l_k whose
+    hypernetwork output is zero for every parameter of the sample ``mus``
+    ([B][3]) is dropped, with column k of U^l and of V^l and the matching
+    output of f_hyper (row k of the last layer's W_K and entry k of c_K); the
+    ranks shrink accordingly.  A layer that would lose every coefficient keeps
+    its first one (which is zero, so the network is unchanged).  The biases
+    and the widths stay.  Returns a dict with the kept mask ``keep``
+    ([r_total] bool), the new ranks ``r``, the factor lists ``U``, ``V``,
+    ``b``, the hypernetwork widths ``H`` and parameters ``theta``."""
+    s, _ = hyper_forward(H, theta, mus)
+    alive = np.any(s != 0.0, axis=0)
+    keep, o = [], 0
+    for rl in net.r:
+        k = alive[o:o + rl].copy()
+        if not k.any():
+            k[0] = True
+        keep.append(k)
+        o += rl
+    U = [np.asarray(u)[:, k] for u, k in zip(net.U, keep)]
+    V = [np.asarray(v)[:, k] for v, k in zip(net.V, keep)]
+    keep_all = np.concatenate(keep)
+    layers = hyper_unpack(H, np.asarray(theta))
+    WK, cK = layers[-1]
+    layers[-1] = (WK[keep_all, :], cK[keep_all])
+    theta_t = np.concatenate([np.concatenate([W.ravel(), c]) for W, c in layers])
+    H_t = list(H[:-1]) + [int(keep_all.sum())]
+    return {"keep": keep_all, "r": [int(k.sum()) for k in keep], "U": U, "V": V,
+            "b": [np.asarray(x) for x in net.b], "H": H_t, "theta": theta_t}
 
 
 def lrnr_basis_grad(net, s_list, mu, pts, cfg=None):

@@ -674,3 +674,76 @@ def test_pod_basis_is_the_leading_singular_subspace_in_order():
     u = np.linalg.svd(Z, full_matrices=False)[0]
     assert not check(u[:, -8:], 8)
     assert not check(u[:, [1, 0, 2, 3, 4, 5, 6, 7]], 8)
+
+
+# ----------------------------------------------------- truncation (Section 4)
+
+def _trunc_case(seed=11):
+    """Small net, a hypernetwork whose last layer sends some outputs to
+    clearly negative pre-activations for every mu (row of W_K zero, c_K = -5):
+    those coefficients are zero at every parameter, the others positive."""
+    w = wl.small_lrnr(0, 512)
+    H = [3, 16, 16, sum(w.net.r)]
+    theta = wl.hyper_init(H, seed=7).astype(np.float64)
+    layers = orc.hyper_unpack(H, theta)
+    WK, cK = layers[-1]
+    dead = np.zeros(H[-1], bool)
+    dead[[3, 5, 6, 9, 10, 11, 12, 13, 14, 15, 16, 17]] = True   # layer 2 keeps 1 (index 2)
+    # (layer blocks of the flat s: [0,2) [2,10) [10,18) [18,26) [26,27))
+    WK[dead, :] = 0.0
+    cK[dead] = -5.0
+    cK[~dead] = np.abs(cK[~dead]) + 2.0
+    theta = np.concatenate([np.concatenate([W.ravel(), c]) for W, c in layers])
+    mus = wl.make_mu(np.random.Generator(np.random.PCG64(seed)), 6).astype(np.float64)
+    return w, H, theta, mus, dead
+
+
+def test_truncate_drops_the_zero_coefficients_and_keeps_one_per_layer():
+    w, H, theta, mus, dead = _trunc_case()
+    t = orc.truncate(w.net, H, theta, mus)
+    # hand count per layer (r = 2, 8, 8, 8, 1): layer 1 keeps 2; layer 2 drops
+    # indices 3, 5, 6, 9 -> keeps 2, 4, 7, 8; layer 3 (10..17) loses all and
+    # keeps its first; layer 4 and the output keep everything
+    assert t["r"] == [2, 4, 1, 8, 1]
+    expect = ~dead
+    expect[10] = True
+    assert np.array_equal(t["keep"], expect)
+    assert t["H"] == H[:-1] + [16]
+    for l, (u, v) in enumerate(zip(t["U"], t["V"])):
+        assert u.shape == (w.net.M[l + 1], t["r"][l]) and v.shape == (w.net.M[l], t["r"][l])
+
+
+def test_truncated_net_and_hypernetwork_reproduce_the_full_ones():
+    """Exactness: the dropped coefficients are zero at every sampled mu, so
+    U^l diag(s^l) V^lT is unchanged and the truncated hypernetwork's outputs
+    are the full one's kept outputs: loss and jets agree to rounding."""
+    w, H, theta, mus, dead = _trunc_case()
+    t = orc.truncate(w.net, H, theta, mus)
+    s_full, _ = orc.hyper_forward(H, theta, mus)
+    s_tr, _ = orc.hyper_forward(t["H"], t["theta"], mus)
+    assert np.array_equal(s_tr, s_full[:, t["keep"]])
+    assert np.all(s_full[:, ~t["keep"]] == 0.0)
+    net_t = wl.Net(M=w.net.M, r=t["r"], U=t["U"], V=t["V"], b=t["b"], s=[])
+    for b in range(len(mus)):
+        sf = w.net.split_s(s_full[b])
+        st = net_t.split_s(s_tr[b])
+        lf, gf, _ = orc.lrnr_loss(w.net, sf, mus[b], w.pts, {}, with_grad=True)
+        lt, gt, _ = orc.lrnr_loss(net_t, st, mus[b], w.pts, {}, with_grad=True)
+        np.testing.assert_allclose(lt, lf, rtol=1e-12, atol=0)
+        # the kept coefficients' gradients are the full net's at those indices
+        np.testing.assert_allclose(gt, gf[t["keep"]], rtol=1e-10, atol=1e-12 * np.abs(gf).max())
+        jf = orc.lrnr_forward_jets(w.net, sf, w.pts.xt_r[:64])
+        jt = orc.lrnr_forward_jets(net_t, st, w.pts.xt_r[:64])
+        np.testing.assert_allclose(jt, jf, rtol=1e-11, atol=1e-12 * np.abs(jf).max())
+
+
+def test_truncate_keeps_everything_when_no_output_vanishes():
+    w = wl.small_lrnr(0, 64)
+    H = [3, 8, sum(w.net.r)]
+    theta = wl.hyper_init(H, seed=3).astype(np.float64)
+    layers = orc.hyper_unpack(H, theta)
+    layers[-1][0][:] = 0.0          # outputs = c_K in [0.5, 1.5): all positive
+    theta = np.concatenate([np.concatenate([W.ravel(), c]) for W, c in layers])
+    t = orc.truncate(w.net, H, theta, np.array([[1.0, 0.5, 0.5]]))
+    assert t["r"] == list(w.net.r) and t["keep"].all()
+    assert np.array_equal(t["theta"], theta)
