@@ -577,7 +577,9 @@ def run_pipeline(args, torch, api, wl):
     steps (lr 1e-3) on the hypernetwork and the biases over 64 parameter
     samples (32 from each domain of Section 4) sharing the 65536 training
     points, then 100 steps on all of eq. 3.4 (U and V too, R_orth weight 1e-3)
-    over 16 of them; (2) a FastLRNR (r_hat = 32) built from snapshots at
+    over 16 of them, then the truncation of Section 4 (coefficients that f_hyper
+    sets to zero at every training sample are dropped); (2) a FastLRNR
+    (r_hat = 32) built from snapshots at
     f_hyper of 8 of those samples; (3) for every bounded test case of the
     reference leg, s_init = f_hyper(mu) and 200 Adam steps with the LRNR and
     with the FastLRNR gradient, the L1 relative error against the reference
@@ -625,6 +627,10 @@ def run_pipeline(args, torch, api, wl):
             api.adam_step(p_, m_, v_, g_, k)
     torch.cuda.synchronize()
     meta_s = time.time() - t0
+    # truncation (Section 4): coefficients f_hyper sets to zero at every
+    # training sample leave the net with their columns of U and V
+    r_full = list(net.r)
+    net, f, keep = api.truncate(net, f, mu_tr)
     s_snap = api.hyper_forward(f, mu_tr[::8].contiguous())
     fast = api.FastLRNR(net, s_snap, torch.tensor(w.extra["xt_snap"], device="cuda"),
                         w.extra["r_hat"])
@@ -682,6 +688,7 @@ def run_pipeline(args, torch, api, wl):
         "meta_objective_first": objs[0], "meta_objective_theta_b_last": objs[1],
         "meta_objective_bases_first": objs[2], "meta_objective_bases_last": objs[3],
         "meta_phase_s": meta_s,
+        "ranks_before_truncation": r_full, "ranks_after_truncation": list(net.r),
         "l1_meta_init_median": float(np.median(init)),
         "l1_lrnr_final_median": float(np.median([c["lrnr_l1"][-1] for c in cases])),
         "l1_fastlrnr_final_median": float(np.median([c["fastlrnr_l1"][-1] for c in cases])),

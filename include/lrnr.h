@@ -523,6 +523,31 @@ int32_t lrnr_hyper_backward(const lrnr_hyper* f, const lrnr_net* net, int32_t B,
 size_t lrnr_hyper_workspace_size(const lrnr_hyper* f, int32_t B);
 
 /*
+ * Truncation after meta-learning (Section 4): over B parameter samples
+ * mu [dev] [B][3], coefficient k of layer l is kept when f_hyper(mu_b)[k] is
+ * nonzero for some b (the ReLU output is exactly zero otherwise, decided in
+ * FP32); dropped coefficients lose their columns of U^l and V^l and their
+ * hypernetwork output (row of W_K, entry of c_K).  A layer with no kept
+ * coefficient keeps its first one (zero at every sample, so the network is
+ * unchanged).  The widths and the biases stay.
+ *  r_out     [host] [L+1] out: the new ranks (r_out[0] = 0)
+ *  keep      [host] [r_total] out: 1 for a kept coefficient, else 0; may be NULL
+ *  U_out     [dev] out: the truncated U, packed as an lrnr_net with ranks r_out
+ *                  (room for the full U); V_out likewise for V
+ *  theta_out [dev] out: the truncated hypernetwork (widths H[0..K-1] and
+ *                  H[K] = the new r_total; room for the full theta)
+ *  ws        [dev] lrnr_truncate_workspace_size(f, B) bytes, 256-B aligned
+ * Synchronises the stream (the kept set sizes the outputs).  LRNR_EINVAL when
+ * f's output width differs from the net's r_total.
+ */
+int32_t lrnr_truncate(const lrnr_net* net, const lrnr_hyper* f, int32_t B, const float* mu,
+                      int32_t* r_out, int32_t* keep, float* U_out, float* V_out,
+                      float* theta_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes of lrnr_truncate for B samples (0 if f or B is invalid). */
+size_t lrnr_truncate_workspace_size(const lrnr_hyper* f, int32_t B);
+
+/*
  * Gradient of the physics-informed loss (eq. 3.5 / 3.6 with eq. 4.1; the
  * locality term does not depend on the bases) with respect to the bases, the
  * parameters the meta-learning phase trains besides Theta and b (eq. 3.4):

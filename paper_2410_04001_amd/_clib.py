@@ -162,6 +162,8 @@ SIGNATURES = {
     "lrnr_hyper_backward": (I32, [C.POINTER(LrnrHyper), NETP, I32, P, P, F32, F32, P, P, P, SZ,
                                   P]),
     "lrnr_hyper_workspace_size": (SZ, [C.POINTER(LrnrHyper), I32]),
+    "lrnr_truncate": (I32, [NETP, C.POINTER(LrnrHyper), I32, P, P, P, P, P, P, P, SZ, P]),
+    "lrnr_truncate_workspace_size": (SZ, [C.POINTER(LrnrHyper), I32]),
     "lrnr_rows_mean": (I32, [P, I32, I64, P, P]),
     "lrnr_orth_reg": (I32, [NETP, P, P, P, P]),
     "lrnr_basis_grad": (I32, [NETP, P, P, PTSP, CFGP, P, P, P, SZ, P]),

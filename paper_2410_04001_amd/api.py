@@ -441,6 +441,28 @@ def hyper_backward(f, net, mu, s_bar, gamma, lambda_sparse, ws=None):
     return g, r
 
 
+def truncate(net, f, mu, ws=None):
+    """Truncation after meta-learning (lrnr_truncate): drops the coefficients
+    that f_hyper sets to zero at every mu [B][3], with their columns of U and
+    V and their hypernetwork outputs.  Returns (DeviceNet with the new ranks,
+    Hyper of the truncated map, keep mask as a host bool array)."""
+    ws = ws or _ws(mu.device)
+    wp, wn = ws.ptr_size(cl.lib().lrnr_truncate_workspace_size(f.c(), mu.shape[0]))
+    U = torch.empty_like(net.U)
+    V = torch.empty_like(net.V)
+    theta = torch.empty_like(f.theta)
+    r_out = (C.c_int32 * (net.L + 1))()
+    keep = (C.c_int32 * net.r_total)()
+    cl.check(cl.lib().lrnr_truncate(net.c(), f.c(), mu.shape[0], _p(mu), r_out, keep, _p(U),
+                                    _p(V), _p(theta), wp, wn, _stream()), "lrnr_truncate")
+    r = [int(x) for x in r_out[1:]]
+    nU = sum(net.M[l] * r[l - 1] for l in range(1, net.L + 1))
+    nV = sum(net.M[l - 1] * r[l - 1] for l in range(1, net.L + 1))
+    H = f.H[:-1] + [sum(r)]
+    tnet = DeviceNet(net.M, r, U[:nU], V[:nV], net.b)
+    return tnet, Hyper(H, theta[:Hyper.n_params(H)]), np.array(keep[:], dtype=bool)
+
+
 def meta_grad(f, net, mu, pts, cfg, gamma, lambda_sparse, ws=None):
     """One gradient of the meta objective with fixed bases: s = f_hyper(mu),
     the batched loss gradient at s, then the hypernetwork backward.  Returns

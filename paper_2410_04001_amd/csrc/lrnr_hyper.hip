@@ -15,6 +15,9 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "lrnr_internal.h"
 
 namespace lrnr {
@@ -223,6 +226,70 @@ __global__ void __launch_bounds__(kOrthThreads) orth_reg_kernel(KNet k, float* v
   if (tid == 0 && value) value[0] = (float)red[0];
 }
 
+// Truncation after meta-learning: alive[m] = 1 when f_hyper's output m is
+// nonzero for some sample (the ReLU output is exactly zero otherwise).
+__global__ void __launch_bounds__(kHyperThreads) output_alive_kernel(const float* s, int B, int R,
+                                                                     int* alive) {
+  const int m = blockIdx.x * kHyperThreads + threadIdx.x;
+  if (m >= R) return;
+  int any = 0;
+  for (int b = 0; b < B; ++b) any |= s[(int64_t)b * R + m] != 0.f;
+  alive[m] = any;
+}
+
+// Gathers of the truncated factors: src[j] is the old flat coefficient index
+// of new coefficient j (layer by layer, ascending).  Thread e of the grid
+// strides over the U, V and theta outputs.
+struct KTrunc {
+  KNet old_net, new_net;
+  const int* src;          // [new r_total]
+  float* U;
+  float* V;
+  const float* theta;
+  float* theta_out;
+  int64_t theta_head;      // entries before the last layer's W_K (copied as is)
+  int HK1;                 // H[K-1]
+  int R_new;
+  int64_t nU, nV, nT;      // output sizes
+};
+
+__global__ void __launch_bounds__(kHyperThreads) truncate_gather_kernel(KTrunc t) {
+  const int64_t stride = (int64_t)gridDim.x * kHyperThreads;
+  const int64_t e0 = (int64_t)blockIdx.x * kHyperThreads + threadIdx.x;
+  const KNet& o = t.old_net;
+  const KNet& n = t.new_net;
+  for (int64_t e = e0; e < t.nU + t.nV; e += stride) {
+    const bool isU = e < t.nU;
+    const int64_t q = isU ? e : e - t.nU;
+    int l = 1;
+    const int* off = isU ? n.offU : n.offV;
+    while (l < n.L && q >= off[l + 1]) ++l;
+    const int64_t w = q - off[l];
+    const int rn = n.r[l], ro = o.r[l];
+    const int row = (int)(w / rn), j = (int)(w - (int64_t)row * rn);
+    const int k = t.src[n.offS[l] + j] - o.offS[l];   // old column in the layer
+    if (isU)
+      t.U[e] = o.U[o.offU[l] + (int64_t)row * ro + k];
+    else
+      t.V[q] = o.V[o.offV[l] + (int64_t)row * ro + k];
+  }
+  for (int64_t e = e0; e < t.nT; e += stride) {
+    float v;
+    if (e < t.theta_head) {
+      v = t.theta[e];
+    } else if (e < t.theta_head + (int64_t)t.R_new * t.HK1) {
+      const int64_t q = e - t.theta_head;
+      const int j = (int)(q / t.HK1), i = (int)(q - (int64_t)j * t.HK1);
+      v = t.theta[t.theta_head + (int64_t)t.src[j] * t.HK1 + i];
+    } else {
+      const int j = (int)(e - t.theta_head - (int64_t)t.R_new * t.HK1);
+      const int64_t old_c = t.theta_head + (int64_t)o.r_total * t.HK1;
+      v = t.theta[old_c + t.src[j]];
+    }
+    t.theta_out[e] = v;
+  }
+}
+
 int32_t make_khyper(const lrnr_hyper* f, KHyper* k) {
   if (!f) return fail(LRNR_EINVAL, "NULL hypernetwork");
   if (f->K < 1 || f->K > LRNR_MAX_LAYERS) return fail(LRNR_EINVAL, "hypernetwork K=%d", f->K);
@@ -334,6 +401,106 @@ int32_t lrnr_orth_reg(const lrnr_net* net, float* value, float* grad_U, float* g
                      static_cast<hipStream_t>(stream), k, value, grad_U, grad_V);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "orthogonality term launch");
+  return LRNR_OK;
+}
+
+size_t lrnr_truncate_workspace_size(const lrnr_hyper* f, int32_t B) {
+  KHyper k;
+  if (make_khyper(f, &k) != LRNR_OK || B < 1) return 0;
+  const int R = k.H[k.K];
+  return align256((size_t)B * R * sizeof(float)) + align256((size_t)R * sizeof(int)) +
+         align256((size_t)R * sizeof(int));
+}
+
+int32_t lrnr_truncate(const lrnr_net* net, const lrnr_hyper* f, int32_t B, const float* mu,
+                      int32_t* r_out, int32_t* keep, float* U_out, float* V_out,
+                      float* theta_out, void* ws, size_t ws_bytes, void* stream) {
+  KHyper k;
+  int32_t rc = make_khyper(f, &k);
+  if (rc != LRNR_OK) return rc;
+  KNet kn;
+  int RP, Wp;
+  rc = make_knet(net, &kn, &RP, &Wp);
+  if (rc != LRNR_OK) return rc;
+  const int R = kn.r_total;
+  if (k.H[k.K] != R)
+    return fail(LRNR_EINVAL, "hypernetwork output %d, net r_total %d", k.H[k.K], R);
+  if (B < 1) return fail(LRNR_EINVAL, "B=%d (at least one sample)", B);
+  if (!mu || !r_out || !U_out || !V_out || !theta_out)
+    return fail(LRNR_EINVAL, "NULL mu, r_out, U_out, V_out or theta_out");
+  const size_t need = lrnr_truncate_workspace_size(f, B);
+  if (!ws || ws_bytes < need)
+    return fail(LRNR_ENOMEM, "workspace %zu bytes, need %zu", ws_bytes, need);
+  if ((uintptr_t)ws & 255) return fail(LRNR_EINVAL, "workspace not 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  float* s = reinterpret_cast<float*>(base);
+  int* alive_d = reinterpret_cast<int*>(base + align256((size_t)B * R * sizeof(float)));
+  int* src_d = reinterpret_cast<int*>(base + align256((size_t)B * R * sizeof(float)) +
+                                      align256((size_t)R * sizeof(int)));
+  hipLaunchKernelGGL(hyper_forward_kernel, dim3(B), dim3(kHyperThreads), 0, st, k, mu, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "hypernetwork forward launch");
+  hipLaunchKernelGGL(output_alive_kernel, dim3((R + kHyperThreads - 1) / kHyperThreads),
+                     dim3(kHyperThreads), 0, st, s, B, R, alive_d);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "alive launch");
+  std::vector<int> alive(R);
+  if ((e = hipMemcpyAsync(alive.data(), alive_d, R * sizeof(int), hipMemcpyDeviceToHost, st)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return hip_fail(e, "alive copy");
+  // kept set: the alive coefficients; a layer with none keeps its first
+  std::vector<int> src;
+  KNet nn = kn;
+  int oU = 0, oV = 0, oS = 0;
+  for (int l = 1; l <= kn.L; ++l) {
+    int cnt = 0;
+    for (int j = 0; j < kn.r[l]; ++j)
+      if (alive[kn.offS[l] + j]) {
+        src.push_back(kn.offS[l] + j);
+        ++cnt;
+      }
+    if (cnt == 0) {
+      src.push_back(kn.offS[l]);
+      cnt = 1;
+    }
+    nn.r[l] = cnt;
+    nn.offU[l] = oU;
+    nn.offV[l] = oV;
+    nn.offS[l] = oS;
+    oU += kn.M[l] * cnt;
+    oV += kn.M[l - 1] * cnt;
+    oS += cnt;
+  }
+  nn.r_total = oS;
+  nn.U = U_out;
+  nn.V = V_out;
+  r_out[0] = 0;
+  for (int l = 1; l <= kn.L; ++l) r_out[l] = nn.r[l];
+  if (keep) {
+    for (int m = 0; m < R; ++m) keep[m] = 0;
+    for (int j : src) keep[j] = 1;
+  }
+  if ((e = upload_async(src_d, src.data(), src.size() * sizeof(int), st)) != hipSuccess)
+    return hip_fail(e, "index upload");
+  KTrunc t{};
+  t.old_net = kn;
+  t.new_net = nn;
+  t.src = src_d;
+  t.U = U_out;
+  t.V = V_out;
+  t.theta = f->theta;
+  t.theta_out = theta_out;
+  t.theta_head = k.offW[k.K];
+  t.HK1 = k.H[k.K - 1];
+  t.R_new = oS;
+  t.nU = oU;
+  t.nV = oV;
+  t.nT = t.theta_head + (int64_t)oS * (t.HK1 + 1);
+  const int64_t work = std::max<int64_t>(t.nU + t.nV, t.nT);
+  const int blocks = (int)std::min<int64_t>((work + kHyperThreads - 1) / kHyperThreads, 4096);
+  hipLaunchKernelGGL(truncate_gather_kernel, dim3(blocks), dim3(kHyperThreads), 0, st, t);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "truncation gather launch");
   return LRNR_OK;
 }
 

@@ -205,3 +205,63 @@ def test_basis_grad_matches_oracle(name, make, form):
     assert_close(gU.cpu().numpy(), rU, TOL, f"{name} grad U", blocks=u_blocks(w.net))
     assert_close(gV.cpu().numpy(), rV, TOL, f"{name} grad V", blocks=v_blocks(w.net))
     assert torch.equal(gU, gU2) and torch.equal(gV, gV2)
+
+
+def _trunc_theta(w, H, dead_idx, seed=7):
+    """A hypernetwork whose last layer sends the outputs dead_idx to a
+    pre-activation of -5 at every mu (zero row of W_K, c_K = -5) and keeps
+    the others at least 2 (decisions far from the ReLU's kink)."""
+    theta = wl.hyper_init(H, seed=seed).astype(np.float64)
+    layers = orc.hyper_unpack(H, theta)
+    WK, cK = layers[-1]
+    dead = np.zeros(H[-1], bool)
+    dead[dead_idx] = True
+    WK[dead, :] = 0.0
+    cK[dead] = -5.0
+    cK[~dead] = np.abs(cK[~dead]) + 2.0
+    return np.concatenate([np.concatenate([W.ravel(), c]) for W, c in layers]).astype(np.float32)
+
+
+TRUNC = [("small", lambda: wl.small_lrnr(0, 2048), [3, 5, 6, 9, 10, 11, 12, 13, 14, 15, 16, 17]),
+         ("wide", lambda: wl.big_lrnr(1, 2048), list(range(2, 22, 3)) + list(range(22, 42)))]
+
+
+@pytest.mark.parametrize("name,make,dead", TRUNC, ids=[c[0] for c in TRUNC])
+def test_truncate_matches_oracle(name, make, dead):
+    """Truncation after meta-learning (lrnr_truncate): the kept set and ranks
+    equal the oracle's, the truncated U, V and Theta are the oracle's gathers
+    bitwise, and the truncated net at f'(mu) reproduces the full net's loss
+    and kept s-gradients (the dropped coefficients are zero)."""
+    a = api()
+    w = make()
+    R = w.net.r_total
+    H = [3, 16, 16, R]
+    theta = _trunc_theta(w, H, dead)
+    mus = wl.make_mu(np.random.Generator(np.random.PCG64(11)), 6)
+    f = a.Hyper(H, torch.tensor(theta, device="cuda"))
+    net = a.DeviceNet.from_net(w.net)
+    mu_d = torch.tensor(mus, device="cuda")
+    tnet, tf, keep = a.truncate(net, f, mu_d)
+    torch.cuda.synchronize()
+    ref = orc.truncate(w.net, H, theta.astype(np.float64), mus.astype(np.float64))
+    log(f"[case] truncate {name}: r {w.net.r} -> {tnet.r} (oracle {ref['r']})")
+    assert tnet.r == ref["r"] and np.array_equal(keep, ref["keep"])
+    assert tf.H == ref["H"]
+    assert np.array_equal(tnet.U.cpu().numpy(), np.concatenate([u.ravel() for u in ref["U"]]))
+    assert np.array_equal(tnet.V.cpu().numpy(), np.concatenate([v.ravel() for v in ref["V"]]))
+    assert np.array_equal(tf.theta.cpu().numpy(), ref["theta"].astype(np.float32))
+    # the truncated net and map against the full ones, through the device path
+    pts = a.DevicePoints.from_points(w.pts)
+    s_full = a.hyper_forward(f, mu_d)
+    s_tr = a.hyper_forward(tf, mu_d)
+    torch.cuda.synchronize()
+    assert torch.equal(s_tr, s_full[:, torch.tensor(keep, device="cuda")])
+    for b in (0, 5):
+        gs, _, loss = a.grad_s(tnet, s_tr[b].contiguous(), mu_d[b].contiguous(), pts, a.LossCfg(),
+                               with_b=False)
+        torch.cuda.synchronize()
+        sf = w.net.split_s(s_full[b].cpu().numpy())
+        lf, gf, _ = orc.lrnr_loss(w.net, sf, mus[b].astype(np.float64), w.pts, {},
+                                  with_grad=True)
+        assert_close(loss.cpu().numpy(), lf, TOL, f"truncated {name} loss (mu {b})")
+        assert_close(gs.cpu().numpy(), gf[keep], TOL, f"truncated {name} kept grad_s (mu {b})")
