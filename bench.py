@@ -791,6 +791,28 @@ def run_serving(args, torch, api, wl):
               f"achieved {row['req_per_s']:.1f} req/s", file=sys.stderr, flush=True)
     stats = srv.stats()
     srv.close()
+    # the same stream with several steps per graph launch: fewer launches,
+    # coarser admission (a request joins between launches)
+    rows_multi = []
+    spl = 4 if args.serve_steps_per_launch == 1 else 1
+    if args.serve_rates_multi:
+        srv = serving.Server([(f.net, s0) for f in fasts], K=100, steps_per_launch=spl,
+                             max_slots=256, max_inflight=2, arena_bytes=2 << 30,
+                             max_tiles=1 << 17)
+        reqs = [srv.request(r.id, r.model, r.mu, wl.request_points(st["pt_seed"][r.id],
+                                                                   int(st["n"][r.id])))
+                for r in reqs]
+        serving.replay(srv, reqs[:32], st["arrival"][:32] / 2000.0)
+        for rate in args.serve_rates_multi:
+            done, wall = serving.replay(srv, reqs, st["arrival"] / rate)
+            row = serving.latency_summary(done, wall)
+            row["offered_req_per_s"] = rate
+            row["tuning_pt_steps_per_s"] = row.pop("colloc_pts_per_s") * 100
+            rows_multi.append(row)
+            print(f"# serving ({spl} steps per launch) rate {rate}: p50 {row['p50_ms']:.2f} ms "
+                  f"p99 {row['p99_ms']:.2f} ms achieved {row['req_per_s']:.1f} req/s",
+                  file=sys.stderr, flush=True)
+        srv.close()
     for f in fasts:
         f.close()
     mean_n = float(np.mean(st["n"]))
@@ -800,6 +822,8 @@ def run_serving(args, torch, api, wl):
                     "K=100 Adam steps then a 256x100 grid evaluation",
         "steps_per_launch": args.serve_steps_per_launch,
         "rates": rows,
+        "steps_per_launch_other": spl,
+        "rates_other": rows_multi,
         "engine": {k: stats[k] for k in ("launches", "steps", "evals", "table_uploads",
                                           "peak_active", "arena_peak")},
     }
@@ -942,6 +966,10 @@ def headline(out, full_path):
         legs["serving_rate_achieved_p50_p99_ms"] = [
             [_r(r["offered_req_per_s"]), _r(r["req_per_s"]), _r(r["p50_ms"]), _r(r["p99_ms"])]
             for r in sv["rates"]]
+        if sv.get("rates_other"):
+            legs[f"serving_{sv['steps_per_launch_other']}_steps_per_launch"] = [
+                [_r(r["offered_req_per_s"]), _r(r["req_per_s"]), _r(r["p50_ms"]), _r(r["p99_ms"])]
+                for r in sv["rates_other"]]
     mt = out.get("meta")
     if mt:
         legs["meta_ms_per_step"] = _r(mt["ms_per_meta_step"])
@@ -979,6 +1007,9 @@ def main():
                     default=[50, 100, 200, 500, 1000, 2000])
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-steps-per-launch", type=int, default=1)
+    ap.add_argument("--serve-rates-multi", type=lambda x: [float(v) for v in x.split(",") if v],
+                    default=[500, 1000],
+                    help="rates replayed again with 4 steps per launch (1 if the main run uses more)")
     ap.add_argument("--out", default=os.path.join("gpurun_out", "bench_full.json"),
                     help="file for the full record of every leg")
     ap.add_argument("--copy-calibration", action="store_true",

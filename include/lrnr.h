@@ -316,14 +316,26 @@ typedef struct lrnr_srv_request {
   float* loss_out;                /* [host] [4] loss at the last step, or NULL   */
 } lrnr_srv_request;
 
+/* Completion status of a request (lrnr_srv_done.status). */
+#define LRNR_SRV_OK 0         /* K steps taken, outputs written                  */
+#define LRNR_SRV_NONFINITE 1  /* the loss or its gradient turned non-finite at
+                                 step `steps` + 1: s keeps its last finite value,
+                                 the request stops tuning and its outputs
+                                 (grid, s, the non-finite loss) are written     */
+#define LRNR_SRV_CANCELLED 2  /* cancelled by lrnr_srv_cancel: no outputs       */
+
 typedef struct lrnr_srv_done {
   int64_t id;
-  double arrival, admitted, done;  /* lrnr_srv_clock() times                    */
+  double arrival, admitted, done;  /* lrnr_srv_clock() times (admitted = 0 for a
+                                      request cancelled while waiting)          */
   int32_t model, tiles;
+  int32_t status;                  /* LRNR_SRV_OK, _NONFINITE or _CANCELLED      */
+  int32_t steps;                   /* Adam steps applied to s                    */
 } lrnr_srv_done;
 
 typedef struct lrnr_srv_stats {
-  int64_t submitted, admitted, completed;
+  int64_t submitted, admitted, completed;   /* completed counts every status   */
+  int64_t failed, cancelled;
   int64_t launches, steps, evals, table_uploads;
   int32_t waiting, active, finishing, peak_active;
   int64_t arena_used, arena_peak;
@@ -342,8 +354,18 @@ int64_t lrnr_srv_footprint(const lrnr_srv_cfg* cfg, int32_t model, int64_t n_r, 
 int32_t lrnr_srv_create(const lrnr_srv_cfg* cfg, lrnr_srv** out);
 
 /* Queues a request (thread-safe; validation only, no device work).
- * LRNR_ENOMEM when the request can never fit the arena or tile cap. */
+ * LRNR_EINVAL for a non-finite mu; LRNR_ENOMEM when the request can never fit
+ * the arena or tile cap.  Point values are not scanned: a non-finite point
+ * makes that request, and only it, complete with LRNR_SRV_NONFINITE. */
 int32_t lrnr_srv_submit(lrnr_srv* srv, const lrnr_srv_request* req);
+
+/* Cancels request id (call from the thread that polls).  A waiting request
+ * completes at once; an admitted one leaves the step table before the next
+ * launch and completes once the launches already queued have run; either way
+ * its done record has status LRNR_SRV_CANCELLED and no outputs are written.
+ * The other requests are unaffected (bitwise).  LRNR_EINVAL when id is not
+ * waiting or tuning (unknown, completed, or already being evaluated). */
+int32_t lrnr_srv_cancel(lrnr_srv* srv, int64_t id);
 
 /* One scheduling pass, never waiting on the device except to bound the
  * queued launches: delivers finished requests, admits waiting ones and

@@ -16,6 +16,7 @@ MAX_WIDTH = 256
 MAX_RANK = 32
 
 OK, EINVAL, ENOMEM, EHIP, ESINGULAR, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+SRV_OK, SRV_NONFINITE, SRV_CANCELLED = 0, 1, 2
 
 
 class LrnrNet(C.Structure):
@@ -108,12 +109,14 @@ class LrnrSrvDone(C.Structure):
     _fields_ = [
         ("id", C.c_int64), ("arrival", C.c_double), ("admitted", C.c_double),
         ("done", C.c_double), ("model", C.c_int32), ("tiles", C.c_int32),
+        ("status", C.c_int32), ("steps", C.c_int32),
     ]
 
 
 class LrnrSrvStats(C.Structure):
     _fields_ = [
         ("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+        ("failed", C.c_int64), ("cancelled", C.c_int64),
         ("launches", C.c_int64), ("steps", C.c_int64), ("evals", C.c_int64),
         ("table_uploads", C.c_int64),
         ("waiting", C.c_int32), ("active", C.c_int32), ("finishing", C.c_int32),
@@ -145,6 +148,7 @@ SIGNATURES = {
     "lrnr_srv_submit": (I32, [P, C.POINTER(LrnrSrvRequest)]),
     "lrnr_srv_poll": (I32, [P, C.POINTER(I32), C.POINTER(I32)]),
     "lrnr_srv_take_done": (I32, [P, C.POINTER(LrnrSrvDone), I32, C.POINTER(I32)]),
+    "lrnr_srv_cancel": (I32, [P, I64]),
     "lrnr_srv_get_stats": (I32, [P, C.POINTER(LrnrSrvStats)]),
     "lrnr_srv_destroy": (I32, [P]),
     "fastlrnr_build": (I32, [NETP, P, I32, P, I64, C.POINTER(I32), C.POINTER(P), P]),

@@ -108,7 +108,9 @@ struct KTask {
   float* s_upd;             // the coefficients to update (inst.s)
   float* m;                 // [r_total]
   float* v;                 // [r_total]
-  int* step;                // Adam step counter, incremented on the device
+  int* step;                // Adam step counter, incremented on the device;
+                            // kTaskFailed is or-ed in when the loss or its
+                            // gradient turns non-finite (the task stops)
   int steps_max;            // no update once *step reaches this
   int pad_;
 };

@@ -6,6 +6,7 @@
 #include <algorithm>
 
 #include "lrnr_internal.h"
+#include "lrnr_task_status.h"
 
 namespace lrnr {
 
@@ -130,6 +131,7 @@ __global__ __launch_bounds__(kTableReduceThreads) void table_reduce_kernel(KTabl
     const float* sref = T.s_ref;
     const bool loc = T.lambda_loc != 0.f && sref != nullptr;
     const int nchunk = (G + kRedChunk - 1) / kRedChunk;
+    int nonfinite = 0;
     for (int e = tid; e < E; e += kTableReduceThreads) {
       double acc = 0.0;
       for (int c = 0; c < nchunk; ++c) {
@@ -138,17 +140,19 @@ __global__ __launch_bounds__(kTableReduceThreads) void table_reduce_kernel(KTabl
       }
       if (e < 4) {
         sums[e] = acc;
+        nonfinite |= !isfinite(acc);
       } else if (e < 4 + r_total) {
         const int k = e - 4;
         if (loc) acc += (double)T.lambda_loc * sgn(s[k] - sref[k]);
         const float g = (float)acc;
         gsh[k] = g;
+        nonfinite |= !isfinite(g);
         if (T.grad_s) T.grad_s[k] = g;
       } else {
         T.grad_b[e - 4 - r_total] = (float)acc;
       }
     }
-    __syncthreads();
+    const bool failed = __syncthreads_or(nonfinite) != 0;
     if (tid == 0 && T.loss) {
       const int64_t n_r = T.inst.n_r, n_0 = T.inst.n_0, n_b = T.inst.n_b;
       const double ti = n_r ? (double)T.w_r / n_r * sums[0] : 0.0;
@@ -162,7 +166,12 @@ __global__ __launch_bounds__(kTableReduceThreads) void table_reduce_kernel(KTabl
       T.loss[2] = (float)t0;
       T.loss[3] = (float)tb;
     }
-    if (adam_on) {
+    if (adam_on && failed) {
+      // a non-finite loss or gradient: s, m and v stay as they are and the
+      // task is finished (its counter now exceeds any step limit)
+      __syncthreads();  // every thread has read *T.step
+      if (tid == 0) *T.step = step | kTaskFailed;
+    } else if (adam_on) {
       // Adam (Kingma & Ba), bias-corrected, step counted from 1
       const int stp = step + 1;
       const float bc1 = (float)(1.0 - pow((double)adam.beta1, (double)stp));

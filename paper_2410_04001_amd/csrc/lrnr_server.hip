@@ -14,12 +14,14 @@
 // multi-step graph never overshoots.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <mutex>
 #include <vector>
 
 #include "lrnr_internal.h"
+#include "lrnr_task_status.h"
 #include "srv_sched.h"
 
 using namespace lrnr;
@@ -46,6 +48,7 @@ struct Req {
   int slot = -1;
   double admitted = 0;
   int steps_issued = 0;
+  bool cancelled = false;
 };
 
 struct Batch {       // requests whose evaluation and copies are queued
@@ -267,6 +270,8 @@ struct lrnr_srv {
           (e = hipMemcpyAsync(h + grid_pts, base + r.fp.s, (size_t)rt * 4,
                               hipMemcpyDeviceToHost, stream)) != hipSuccess ||
           (e = hipMemcpyAsync(h + grid_pts + rt_max, base + r.fp.loss, 16,
+                              hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+          (e = hipMemcpyAsync(h + grid_pts + rt_max + 4, base + r.fp.step, 4,
                               hipMemcpyDeviceToHost, stream)) != hipSuccess)
         return e;
     }
@@ -277,11 +282,6 @@ struct lrnr_srv {
   void deliver(Batch& b) {
     const double t = clock_s();
     for (Req& r : b.reqs) {
-      const float* h = host_out + (size_t)r.slot * out_stride;
-      const int rt = models[r.in.model].k.r_total;
-      if (r.in.u_out) std::memcpy(r.in.u_out, h, (size_t)grid_pts * 4);
-      if (r.in.s_out) std::memcpy(r.in.s_out, h + grid_pts, (size_t)rt * 4);
-      if (r.in.loss_out) std::memcpy(r.in.loss_out, h + grid_pts + rt_max, 16);
       lrnr_srv_done d{};
       d.id = r.in.id;
       d.arrival = r.in.arrival;
@@ -289,11 +289,78 @@ struct lrnr_srv {
       d.done = t;
       d.model = r.in.model;
       d.tiles = r.fp.tiles;
+      if (r.cancelled) {
+        d.status = LRNR_SRV_CANCELLED;
+        ++st.cancelled;
+      } else {
+        const float* h = host_out + (size_t)r.slot * out_stride;
+        const int rt = models[r.in.model].k.r_total;
+        if (r.in.u_out) std::memcpy(r.in.u_out, h, (size_t)grid_pts * 4);
+        if (r.in.s_out) std::memcpy(r.in.s_out, h + grid_pts, (size_t)rt * 4);
+        if (r.in.loss_out) std::memcpy(r.in.loss_out, h + grid_pts + rt_max, 16);
+        int step;
+        std::memcpy(&step, h + grid_pts + rt_max + 4, 4);
+        d.status = (step & kTaskFailed) ? LRNR_SRV_NONFINITE : LRNR_SRV_OK;
+        d.steps = step & ~kTaskFailed;
+        if (d.status != LRNR_SRV_OK) ++st.failed;
+      }
       done.push_back(d);
       alloc.release(r.off, r.fp.total);
       free_slots.push_back(r.slot);
       ++st.completed;
     }
+  }
+
+  // Cancelled admitted requests leave the step table now; their arena blocks
+  // are released once the launches already queued (which may still read
+  // them) have run.
+  hipError_t drop_cancelled() {
+    Batch b;
+    std::vector<Req> keep;
+    keep.reserve(active.size());
+    for (Req& r : active) {
+      if (r.cancelled) {
+        tiles_active -= r.fp.tiles;
+        b.reqs.push_back(r);
+      } else {
+        keep.push_back(r);
+      }
+    }
+    if (b.reqs.empty()) return hipSuccess;
+    active.swap(keep);
+    dirty = true;
+    hipError_t e;
+    if ((e = event(&b.ev)) != hipSuccess || (e = hipEventRecord(b.ev, stream)) != hipSuccess)
+      return e;
+    finishing.push_back(std::move(b));
+    return hipSuccess;
+  }
+
+  int32_t cancel(int64_t id) {
+    {
+      std::lock_guard<std::mutex> lock(mu_wait);
+      for (auto it = waiting.begin(); it != waiting.end(); ++it) {
+        if (it->in.id != id) continue;
+        lrnr_srv_done d{};
+        d.id = id;
+        d.arrival = it->in.arrival;
+        d.done = clock_s();
+        d.model = it->in.model;
+        d.tiles = it->fp.tiles;
+        d.status = LRNR_SRV_CANCELLED;
+        done.push_back(d);
+        waiting.erase(it);
+        ++st.cancelled;
+        ++st.completed;
+        return LRNR_OK;
+      }
+    }
+    for (Req& r : active) {
+      if (r.in.id != id || r.cancelled) continue;
+      r.cancelled = true;
+      return LRNR_OK;
+    }
+    return fail(LRNR_EINVAL, "request %lld is not waiting or tuning", (long long)id);
   }
 
   int32_t poll() {
@@ -335,6 +402,7 @@ struct lrnr_srv {
       }
     }
     if (active.size() > (size_t)st.peak_active) st.peak_active = (int32_t)active.size();
+    if ((e = drop_cancelled()) != hipSuccess) return hip_fail(e, "cancellation");
     // 3. queue the next step launch
     if (active.empty() || (int)inflight.size() >= cfg.max_inflight) return LRNR_OK;
     if (dirty) {
@@ -486,7 +554,8 @@ int32_t lrnr_srv_create(const lrnr_srv_cfg* cfg, lrnr_srv** out) {
   S->cfg = *cfg;
   S->cfg.models = nullptr;  // copied into S->models
   S->grid_pts = (int64_t)cfg->grid_nx * cfg->grid_nt;
-  S->out_stride = (int)((S->grid_pts + S->rt_max + 4 + 63) & ~63);
+  // per slot: grid values, s, loss [4], the Adam step counter
+  S->out_stride = (int)((S->grid_pts + S->rt_max + 5 + 63) & ~63);
   S->alloc.reset(cfg->arena_bytes);
   hipError_t e = hipSuccess;
   auto bad = [&](const char* what) {
@@ -556,6 +625,8 @@ int32_t lrnr_srv_submit(lrnr_srv* S, const lrnr_srv_request* req) {
   if (!S || !req) return fail(LRNR_EINVAL, "NULL engine or request");
   if (req->model < 0 || req->model >= (int)S->models.size())
     return fail(LRNR_EINVAL, "model %d outside [0,%zu)", req->model, S->models.size());
+  if (!std::isfinite(req->mu[0]) || !std::isfinite(req->mu[1]) || !std::isfinite(req->mu[2]))
+    return fail(LRNR_EINVAL, "request %lld: non-finite mu", (long long)req->id);
   lrnr_points pts{req->xt_r, req->n_r, req->x_0, req->n_0, req->t_b, req->n_b};
   int32_t st = check_points(&pts);
   if (st) return st;
@@ -586,6 +657,11 @@ int32_t lrnr_srv_poll(lrnr_srv* S, int32_t* n_waiting, int32_t* n_active) {
     *n_active = (int32_t)S->active.size() + f;
   }
   return st;
+}
+
+int32_t lrnr_srv_cancel(lrnr_srv* S, int64_t id) {
+  if (!S) return fail(LRNR_EINVAL, "NULL engine");
+  return S->cancel(id);
 }
 
 int32_t lrnr_srv_take_done(lrnr_srv* S, lrnr_srv_done* out, int32_t cap, int32_t* n) {

@@ -130,6 +130,11 @@ class Server:
         cl.check(cl.lib().lrnr_srv_poll(self._h, C.byref(w), C.byref(a)), "lrnr_srv_poll")
         return w.value, a.value
 
+    def cancel(self, rid):
+        """Cancels a waiting or tuning request (lrnr_srv_cancel); its record
+        then completes with status SRV_CANCELLED and no outputs."""
+        cl.check(cl.lib().lrnr_srv_cancel(self._h, int(rid)), "lrnr_srv_cancel")
+
     def take_done(self, cap=256):
         out = (cl.LrnrSrvDone * cap)()
         n = C.c_int32()
@@ -139,7 +144,8 @@ class Server:
             d = out[k]
             req = self._pending.pop(d.id)
             req.record = {"id": d.id, "arrival": d.arrival, "admitted": d.admitted,
-                          "done": d.done, "model": d.model, "tiles": d.tiles}
+                          "done": d.done, "model": d.model, "tiles": d.tiles,
+                          "status": d.status, "steps": d.steps}
             done.append(req)
         return done
 

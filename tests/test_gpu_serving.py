@@ -210,3 +210,74 @@ def test_serving_alone_equals_mix_bitwise_wide_models(wide_models):
                 assert np.all(np.isfinite(x))
                 assert np.array_equal(x, y), (kw, r.id)
     log(f"  wide models: every request bitwise equal alone and in the mixes")
+
+
+def test_serving_rejects_nonfinite_mu(models):
+    from paper_2410_04001_amd import _clib as cl
+    srv = make_server(models)
+    (r,) = requests(srv, [(0, 1, 1024, 11)])
+    r.mu = np.array([np.nan, 1.0, 1.0], np.float32)
+    rc = r.c(0.0)
+    import ctypes as C
+    assert cl.lib().lrnr_srv_submit(srv._h, C.byref(rc)) == cl.EINVAL
+    r.mu = np.array([1.0, np.inf, 1.0], np.float32)
+    rc = r.c(0.0)
+    assert cl.lib().lrnr_srv_submit(srv._h, C.byref(rc)) == cl.EINVAL
+    assert srv.stats()["submitted"] == 0
+    srv.close()
+
+
+def test_serving_failure_isolation_and_cancellation(models):
+    """A request with a non-finite point (an input value) completes alone with
+    status NONFINITE after 0 steps (s left at s_init, grid written); one
+    request cancelled while waiting and one cancelled while tuning complete
+    with status CANCELLED and no outputs; every other request in the mix is
+    bitwise equal to its solo run."""
+    from paper_2410_04001_amd import _clib as cl
+    w, net, s0, fasts = models
+    specs = SPECS[:4]
+    alone = {sp[0]: run_alone(models, sp) for sp in specs}
+    srv = make_server(models)
+    reqs = requests(srv, specs)
+    pts = wl.request_points(21, 4000)
+    pts.xt_r[17, 0] = np.nan
+    mu = wl.make_mu(np.random.Generator(np.random.PCG64(28)), 1)[0]
+    bad = srv.request(100, 1, mu, pts)
+    c_wait, c_run = requests(srv, [(101, 0, 2000, 22), (102, 2, 9000, 23)])
+    srv.submit(reqs[0])
+    srv.submit(bad)
+    srv.submit(c_run)
+    for _ in range(6):
+        srv.poll()
+    srv.submit(c_wait)
+    srv.cancel(101)             # still waiting: completes at once
+    srv.cancel(102)             # tuning: leaves the table before the next launch
+    for r in reqs[1:]:
+        srv.submit(r)
+    done = srv.run_until_done()
+    st = srv.stats()
+    srv.close()
+    rec = {r.id: r.record for r in done}
+    log(f"  statuses { {k: (v['status'], v['steps']) for k, v in rec.items()} }, stats "
+        f"failed {st['failed']} cancelled {st['cancelled']} completed {st['completed']}")
+    assert len(done) == len(specs) + 3
+    assert st["failed"] == 1 and st["cancelled"] == 2 and st["completed"] == len(specs) + 3
+    assert rec[100]["status"] == cl.SRV_NONFINITE and rec[100]["steps"] == 0
+    assert not np.isfinite(bad.loss[0])
+    fast = fasts[1]
+    assert np.array_equal(bad.s, s0.cpu().numpy()[:fast.net.r_total])
+    assert np.all(np.isfinite(bad.u))
+    for c in (c_wait, c_run):
+        assert rec[c.id]["status"] == cl.SRV_CANCELLED
+        assert np.all(np.isnan(c.u)) and np.all(np.isnan(c.s)) and np.all(np.isnan(c.loss))
+    assert rec[101]["admitted"] == 0.0
+    for r in reqs:
+        assert rec[r.id]["status"] == cl.SRV_OK and rec[r.id]["steps"] == K
+        for x, y in zip(outputs(r), alone[r.id]):
+            assert np.array_equal(x, y), r.id
+    srv2 = make_server(models)
+    try:
+        with pytest.raises(cl.LrnrError):
+            srv2.cancel(12345)          # unknown id
+    finally:
+        srv2.close()
