@@ -233,7 +233,7 @@ def run_fidelity(args, torch, api, wl):
     torch.cuda.synchronize()
     gl = gs_l.double()
     rows = []
-    for r_hat in (8, 12, 16, 24, 32, 48, 64):
+    for r_hat in (4, 8, 12, 16, 24, 32, 48, 64):
         for sel in ("deim", "qdeim"):
             for name, snap in snaps.items():
                 torch.cuda.synchronize()
@@ -521,30 +521,26 @@ def run_meta(args, torch, api, wl):
     ms_b_step = evb[0].elapsed_time(evb[1]) / n_steps
     obj_b = [float(l[:, 0].double().mean()) + lam * float(rr[0]) for l, rr in hist_b]
 
-    # all of eq. 3.4: Theta, b, U and V (basis gradient per sample, its mean,
-    # and R_orth with weight 1e-3) on 8 of the samples, 30 steps
+    # all of eq. 3.4: Theta, b, U and V (the mean basis gradient over the
+    # samples in one fused launch, and R_orth with weight 1e-3) on all 64
+    # samples, 200 steps
     net_u = api.DeviceNet.from_net(w.net)
     theta_u = torch.tensor(wl.hyper_init(H), device="cuda")
     f_u = api.Hyper(H, theta_u)
-    mu8 = mu[:8].contiguous()
-    meta_u = api.MetaStep(f_u, net_u, mu8, pts)
+    meta_u = api.MetaStep(f_u, net_u, mu, pts)
     lam_o = 1e-3
     params = [theta_u, net_u.b, net_u.U, net_u.V]
     mom = [(torch.zeros_like(p), torch.zeros_like(p)) for p in params]
     hist_u = []
     evu = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     evu[0].record()
-    n_u = 30
+    n_u = n_steps
     for k in range(1, n_u + 1):
         g, gb, loss, r = meta_u(cfg, gamma, lam, ws=ws)
-        gUs, gVs = [], []
-        for j in range(8):
-            gU_j, gV_j = api.basis_grad(net_u, meta_u.s[j], mu8[j], pts, cfg, ws=ws)
-            gUs.append(gU_j)
-            gVs.append(gV_j)
+        gU, gV = api.basis_grad_batched(net_u, meta_u.s, mu, pts, cfg, ws=ws)
         ro, gUo, gVo = api.orth_reg(net_u)
-        gU = api.rows_mean(torch.stack(gUs)) + lam_o * gUo
-        gV = api.rows_mean(torch.stack(gVs)) + lam_o * gVo
+        gU = gU + lam_o * gUo
+        gV = gV + lam_o * gVo
         if k in (1, n_u):
             hist_u.append((loss.clone(), r.clone(), ro.clone()))
         for p_, (m_, v_), g_ in zip(params, mom, (g, gb, gU, gV)):
@@ -554,6 +550,13 @@ def run_meta(args, torch, api, wl):
     ms_u_step = evu[0].elapsed_time(evu[1]) / n_u
     obj_u = [float(l[:, 0].double().mean()) + lam * float(rr[0]) + lam_o * float(oo[0])
              for l, rr, oo in hist_u]
+    # the basis gradient alone: the 64-sample mean in one launch, and one
+    # sample (16384 interior + 2048 IC + 2 x 2048 BC evaluation points)
+    s_u = meta_u.s.clone()
+    ms_bg64 = time_calls(torch, lambda: api.basis_grad_batched(net_u, s_u, mu, pts, cfg, ws=ws),
+                         20, 3)
+    s_1, mu_1 = s_u[0].contiguous(), mu[0].contiguous()
+    ms_bg1 = time_calls(torch, lambda: api.basis_grad(net_u, s_1, mu_1, pts, cfg, ws=ws), 20, 3)
 
     n_r = pts.counts[0]
     return {
@@ -565,9 +568,12 @@ def run_meta(args, torch, api, wl):
         "objective_first": obj(0), "objective_last": obj(1),
         "with_biases": {"ms_per_meta_step": ms_b_step, "objective_first": obj_b[0],
                         "objective_last": obj_b[1]},
-        "with_bases_8_samples_30_steps": {"ms_per_meta_step": ms_u_step,
-                                          "objective_first": obj_u[0],
-                                          "objective_last": obj_u[1], "lambda_orth": lam_o},
+        "with_bases_64_samples": {"ms_per_meta_step": ms_u_step, "steps": n_u,
+                                  "objective_first": obj_u[0], "objective_last": obj_u[1],
+                                  "lambda_orth": lam_o,
+                                  "basis_grad_ms_64_samples": ms_bg64,
+                                  "basis_grad_ms_per_sample_batched": ms_bg64 / 64,
+                                  "basis_grad_ms_one_sample": ms_bg1},
         "theta_params": int(theta.numel()),
     }
 
@@ -576,8 +582,8 @@ def run_pipeline(args, torch, api, wl):
     """The workflow of Section 3 on the small net: (1) meta phase, 300 Adam
     steps (lr 1e-3) on the hypernetwork and the biases over 64 parameter
     samples (32 from each domain of Section 4) sharing the 65536 training
-    points, then 100 steps on all of eq. 3.4 (U and V too, R_orth weight 1e-3)
-    over 16 of them, then the truncation of Section 4 (coefficients that f_hyper
+    points, then 300 steps on all of eq. 3.4 (U and V too, R_orth weight 1e-3)
+    over the same samples, then the truncation of Section 4 (coefficients that f_hyper
     sets to zero at every training sample are dropped); (2) a FastLRNR
     (r_hat = 32) built from snapshots at
     f_hyper of 8 of those samples; (3) for every bounded test case of the
@@ -605,24 +611,19 @@ def run_pipeline(args, torch, api, wl):
             objs.append(float(loss[:, 0].double().mean()) + 1e-3 * float(r[0]))
         api.adam_step(f.theta, mt, vt, g, k)
         api.adam_step(net.b, mb, vb, gb, k)
-    # then all of eq. 3.4 (U and V too, with R_orth) on 16 of the samples
-    mu16 = mu_tr[::4].contiguous()
-    meta_u = api.MetaStep(f, net, mu16, pts)
+    # then all of eq. 3.4 (U and V too, with R_orth) on all 64 samples
+    n_bases = 300
+    meta_u = api.MetaStep(f, net, mu_tr, pts)
     params = [f.theta, net.b, net.U, net.V]
     mom = [(torch.zeros_like(p), torch.zeros_like(p)) for p in params]
-    for k in range(1, 101):
+    for k in range(1, n_bases + 1):
         g, gb, loss, r = meta_u(cfg, 1.5, 1e-3, ws=ws)
-        gUs, gVs = [], []
-        for j in range(mu16.shape[0]):
-            gU_j, gV_j = api.basis_grad(net, meta_u.s[j], mu16[j], pts, cfg, ws=ws)
-            gUs.append(gU_j)
-            gVs.append(gV_j)
+        gU, gV = api.basis_grad_batched(net, meta_u.s, mu_tr, pts, cfg, ws=ws)
         ro, gUo, gVo = api.orth_reg(net)
-        if k in (1, 100):
+        if k in (1, n_bases):
             objs.append(float(loss[:, 0].double().mean()) + 1e-3 * float(r[0])
                         + 1e-3 * float(ro[0]))
-        grads = (g, gb, api.rows_mean(torch.stack(gUs)) + 1e-3 * gUo,
-                 api.rows_mean(torch.stack(gVs)) + 1e-3 * gVo)
+        grads = (g, gb, gU + 1e-3 * gUo, gV + 1e-3 * gVo)
         for p_, (m_, v_), g_ in zip(params, mom, grads):
             api.adam_step(p_, m_, v_, g_, k)
     torch.cuda.synchronize()
@@ -682,8 +683,8 @@ def run_pipeline(args, torch, api, wl):
     init = [c["l1_meta_init"] for c in cases]
     return {
         "workload": "small net 64 wide x 4 hidden, rank 8; meta phase 300 steps over 64 samples "
-                    "of the Section 4 domains (Theta and b), then 100 steps over 16 of them "
-                    "(Theta, b, U, V); FastLRNR r_hat=32 "
+                    "of the Section 4 domains (Theta and b), then 300 steps over the same "
+                    "samples (Theta, b, U, V), truncation; FastLRNR r_hat=32 "
                     "from 8 meta samples; 200 fine-tuning steps per bounded test case",
         "meta_objective_first": objs[0], "meta_objective_theta_b_last": objs[1],
         "meta_objective_bases_first": objs[2], "meta_objective_bases_last": objs[3],
@@ -973,6 +974,10 @@ def headline(out, full_path):
     mt = out.get("meta")
     if mt:
         legs["meta_ms_per_step"] = _r(mt["ms_per_meta_step"])
+        wb = mt.get("with_bases_64_samples")
+        if wb:
+            legs["meta_with_bases_ms_per_step"] = _r(wb["ms_per_meta_step"])
+            legs["basis_grad_ms_per_sample"] = _r(wb["basis_grad_ms_per_sample_batched"])
     h["legs"] = legs
     h["full_record"] = full_path
     return h

@@ -576,11 +576,13 @@ size_t lrnr_truncate_workspace_size(const lrnr_hyper* f, int32_t B);
  *   grad_U^l = sum_p sum_c abar^l_{p,c} (s^l * y^l_{p,c})^T,
  *   grad_V^l = sum_p sum_c z^{l-1}_{p,c} ybar^l_{p,c}^T   (c over the jets).
  *  grad_U [dev] packed as net.U, out;  grad_V [dev] packed as net.V, out
- *  ws [dev] workspace of lrnr_basis_grad_workspace_size bytes: per-point
- *  jets and adjoints, about 4 (3 sum_l M_l + 2 sum_l r_l) floats per point.
- * Other arguments as lrnr_grad_s.  Not the hot path: one thread per point,
- * FP32, then a fixed-order FP64 sum over the points per entry (bitwise
- * reproducible).  LRNR_ENOMEM on a short workspace.
+ *  ws [dev] workspace of lrnr_basis_grad_workspace_size bytes, 256-B aligned:
+ *  one record of the U and V entries per wave of 64 points, and the reduced
+ *  jets checkpointed between the sweeps.
+ * Other arguments as lrnr_grad_s.  The terms are formed inside the fused
+ * forward and reverse sweeps (FP32, one lane per point); the per-wave records
+ * are summed in a fixed order in FP64 (bitwise reproducible).  LRNR_ENOMEM
+ * on a short workspace.
  */
 int32_t lrnr_basis_grad(const lrnr_net* net, const float* s, const float* mu,
                         const lrnr_points* pts, const lrnr_loss_cfg* cfg, float* grad_U,
@@ -588,6 +590,21 @@ int32_t lrnr_basis_grad(const lrnr_net* net, const float* s, const float* mu,
 
 /* Workspace bytes of lrnr_basis_grad (0 when the net or points are invalid). */
 size_t lrnr_basis_grad_workspace_size(const lrnr_net* net, const lrnr_points* pts);
+
+/*
+ * The mean over B instances (the samples of the meta objective, eq. 3.4)
+ * of lrnr_basis_grad, in one launch: instance b has coefficients
+ * s [dev] [B][r_total] row b and PDE parameters mu [dev] [B][3] row b, and
+ * all share the net and the points.  grad_U, grad_V as lrnr_basis_grad
+ * ((1/B) sum over b).  ws: lrnr_basis_grad_batched_workspace_size bytes.
+ */
+int32_t lrnr_basis_grad_batched(const lrnr_net* net, int32_t B, const float* s, const float* mu,
+                                const lrnr_points* pts, const lrnr_loss_cfg* cfg,
+                                float* grad_U, float* grad_V, void* ws, size_t ws_bytes,
+                                void* stream);
+
+size_t lrnr_basis_grad_batched_workspace_size(const lrnr_net* net, const lrnr_points* pts,
+                                              int32_t B);
 
 /* Orthogonality term of eq. 3.3 on the net's bases:
  *   R_orth = sum_l ||U^lT U^l - I||_F^2 + ||V^lT V^l - I||_F^2  (all L layers),

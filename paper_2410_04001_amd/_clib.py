@@ -172,6 +172,8 @@ SIGNATURES = {
     "lrnr_orth_reg": (I32, [NETP, P, P, P, P]),
     "lrnr_basis_grad": (I32, [NETP, P, P, PTSP, CFGP, P, P, P, SZ, P]),
     "lrnr_basis_grad_workspace_size": (SZ, [NETP, PTSP]),
+    "lrnr_basis_grad_batched": (I32, [NETP, I32, P, P, PTSP, CFGP, P, P, P, SZ, P]),
+    "lrnr_basis_grad_batched_workspace_size": (SZ, [NETP, PTSP, I32]),
     "lrnr_cdr_reference": (I32, [P, I32, I32, I32, I32, C.c_double, P, P, P]),
     "lrnr_l1_error": (I32, [P, P, I64, P, P]),
     "lrnr_status_string": (C.c_char_p, [I32]),

@@ -493,16 +493,34 @@ def orth_reg(net, with_grad=True):
     return v, gU, gV
 
 
+def _basis_out(net, device):
+    gU = torch.empty(sum(net.M[l] * net.r[l - 1] for l in range(1, net.L + 1)),
+                     dtype=torch.float32, device=device)
+    gV = torch.empty(sum(net.M[l - 1] * net.r[l - 1] for l in range(1, net.L + 1)),
+                     dtype=torch.float32, device=device)
+    return gU, gV
+
+
 def basis_grad(net, s, mu, pts, cfg, ws=None):
     """(grad_U, grad_V) of the loss, packed as net.U and net.V (lrnr_basis_grad)."""
     ws = ws or _ws(s.device)
     wp, wn = ws.ptr_size(cl.lib().lrnr_basis_grad_workspace_size(net.c(), pts.c()))
-    gU = torch.empty(sum(net.M[l] * net.r[l - 1] for l in range(1, net.L + 1)),
-                     dtype=torch.float32, device=s.device)
-    gV = torch.empty(sum(net.M[l - 1] * net.r[l - 1] for l in range(1, net.L + 1)),
-                     dtype=torch.float32, device=s.device)
+    gU, gV = _basis_out(net, s.device)
     cl.check(cl.lib().lrnr_basis_grad(net.c(), _p(s), _p(mu), pts.c(), cfg.c(), _p(gU), _p(gV),
                                       wp, wn, _stream()), "lrnr_basis_grad")
+    return gU, gV
+
+
+def basis_grad_batched(net, s, mu, pts, cfg, ws=None):
+    """The mean over the B rows of s [B][r_total] and mu [B][3] of
+    (grad_U, grad_V) (lrnr_basis_grad_batched)."""
+    B = s.shape[0]
+    ws = ws or _ws(s.device)
+    wp, wn = ws.ptr_size(cl.lib().lrnr_basis_grad_batched_workspace_size(net.c(), pts.c(), B))
+    gU, gV = _basis_out(net, s.device)
+    cl.check(cl.lib().lrnr_basis_grad_batched(net.c(), B, _p(s), _p(mu), pts.c(), cfg.c(),
+                                              _p(gU), _p(gV), wp, wn, _stream()),
+             "lrnr_basis_grad_batched")
     return gU, gV
 
 

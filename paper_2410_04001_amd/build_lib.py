@@ -35,9 +35,9 @@ def sources():
 
 
 # The AGPR-copy rewrite pass of this LLVM crashes on the rank-24 and rank-32
-# gradient kernels under the VGPR-form option, so those tiles are built
-# without it.
-NO_VGPR_FORM = {"lrnr_fused_rp24.hip", "lrnr_fused_rp32.hip"}
+# gradient kernels and on the basis-gradient kernel under the VGPR-form
+# option, so those sources are built without it.
+NO_VGPR_FORM = {"lrnr_fused_rp24.hip", "lrnr_fused_rp32.hip", "lrnr_basis_grad.hip"}
 
 
 def _flags(src):

@@ -207,6 +207,38 @@ def test_basis_grad_matches_oracle(name, make, form):
     assert torch.equal(gU, gU2) and torch.equal(gV, gV2)
 
 
+@pytest.mark.parametrize("name,make", [("small", lambda: wl.small_lrnr(0, 3000)),
+                                       ("rank13", rank16_case)], ids=["small", "rank13"])
+def test_basis_grad_batched_is_the_mean_over_samples(name, make):
+    """lrnr_basis_grad_batched over B = 5 samples (own s and mu, shared
+    points) against the mean of the oracle's per-sample gradients, and its
+    B = 1 case bitwise equal to lrnr_basis_grad."""
+    a = api()
+    w = make()
+    rng = np.random.Generator(np.random.PCG64(23))
+    B = 5
+    s0 = w.net.s_flat()
+    S = np.stack([(s0 * rng.uniform(0.5, 1.5, s0.shape)).astype(np.float32) for _ in range(B)])
+    mus = wl.make_mu(rng, B)
+    log(f"[case] batched basis gradient {name}: M={w.net.M} r={w.net.r} B={B}")
+    net = a.DeviceNet.from_net(w.net)
+    pts = a.DevicePoints.from_points(w.pts)
+    cfg = a.LossCfg()
+    Sd, Md = torch.tensor(S, device="cuda"), torch.tensor(mus, device="cuda")
+    gU, gV = a.basis_grad_batched(net, Sd, Md, pts, cfg)
+    g1U, g1V = a.basis_grad_batched(net, Sd[:1].contiguous(), Md[:1].contiguous(), pts, cfg)
+    h1U, h1V = a.basis_grad(net, Sd[0].contiguous(), Md[0].contiguous(), pts, cfg)
+    torch.cuda.synchronize()
+    assert torch.equal(g1U, h1U) and torch.equal(g1V, h1V)
+    rU, rV = 0.0, 0.0
+    for b in range(B):
+        u, v = orc.lrnr_basis_grad(w.net, w.net.split_s(S[b]), mus[b].astype(np.float64), w.pts,
+                                   {})
+        rU, rV = rU + u / B, rV + v / B
+    assert_close(gU.cpu().numpy(), rU, TOL, f"{name} mean grad U", blocks=u_blocks(w.net))
+    assert_close(gV.cpu().numpy(), rV, TOL, f"{name} mean grad V", blocks=v_blocks(w.net))
+
+
 def _trunc_theta(w, H, dead_idx, seed=7):
     """A hypernetwork whose last layer sends the outputs dead_idx to a
     pre-activation of -5 at every mu (zero row of W_K, c_K = -5) and keeps
