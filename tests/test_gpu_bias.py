@@ -131,8 +131,12 @@ def test_fastlrnr_factored_bias_matches_oracle():
     ops["P"] = P
     l4, rgs, rgsb = orc.fast_loss_factored_bias(w.net, ops, w.net.s, B, sb,
                                                 w.mu[0].astype(np.float64), w.pts, {}, True)
-    assert_close(loss.cpu().numpy(), l4, TOL, "fast factored loss", blocks=LOSS_BLOCKS)
-    assert_close(gs.cpu().numpy(), rgs, TOL, "fast factored grad_s", blocks=s_blocks(w.net))
+    f32 = fp32(lambda: orc.fast_loss_factored_bias(w.net, ops, w.net.s, B, sb, w.mu[0], w.pts,
+                                                   {}, True))
+    assert_close(loss.cpu().numpy(), l4, TOL, "fast factored loss", blocks=LOSS_BLOCKS,
+                 floor=lambda: f32()[0])
+    assert_close(gs.cpu().numpy(), rgs, TOL, "fast factored grad_s", blocks=s_blocks(w.net),
+                 floor=lambda: f32()[1])
     assert_close(gsb.cpu().numpy(), rgsb, TOL, "fast factored grad_sb",
                  blocks=[b.shape[1] for b in B])
     fast.close()

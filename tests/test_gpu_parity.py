@@ -236,9 +236,13 @@ def test_big_net_full_size():
         acc_l += l1.cpu().numpy()
         if k == 3:
             l4, rgs, rgb = orc.lrnr_loss_chunked(w.net, w.net.s, w.mu[0].astype(np.float64), sub, c)
-            assert_close(l1.cpu().numpy(), l4, TOL, "block loss", blocks=LOSS_BLOCKS)
-            assert_close(g1.cpu().numpy(), rgs, TOL, "block grad_s", blocks=s_blocks(w.net))
-            assert_close(b1.cpu().numpy(), rgb, TOL, "block grad_b", blocks=b_blocks(w.net))
+            f32 = fp32(lambda: orc.lrnr_loss_chunked(w.net, w.net.s, w.mu[0], sub, c))
+            assert_close(l1.cpu().numpy(), l4, TOL, "block loss", blocks=LOSS_BLOCKS,
+                         floor=lambda: f32()[0])
+            assert_close(g1.cpu().numpy(), rgs, TOL, "block grad_s", blocks=s_blocks(w.net),
+                         floor=lambda: f32()[1])
+            assert_close(b1.cpu().numpy(), rgb, TOL, "block grad_b", blocks=b_blocks(w.net),
+                         floor=lambda: f32()[2])
     assert_close(gs.cpu().numpy(), acc_s, 1e-5, "full grad_s vs sum of blocks")
     assert_close(gb.cpu().numpy(), acc_b, 1e-5, "full grad_b vs sum of blocks")
     assert_close(loss.cpu().numpy(), acc_l, 1e-5, "full loss vs sum of blocks")
@@ -275,8 +279,12 @@ def test_batched_equals_single_bitwise(width, rank):
     s_list = w.net.split_s(S[2].cpu().numpy())
     l4, rgs, _ = orc.lrnr_loss(w.net, s_list, MU[2].cpu().numpy().astype(np.float64), w.pts, {},
                                with_grad=True)
-    assert_close(gsb[2].cpu().numpy(), rgs, TOL, "batched grad_s", blocks=s_blocks(w.net))
-    assert_close(lb[2].cpu().numpy(), l4, TOL, "batched loss", blocks=LOSS_BLOCKS)
+    mu2 = MU[2].cpu().numpy()
+    f32 = fp32(lambda: orc.lrnr_loss(w.net, s_list, mu2, w.pts, {}, with_grad=True))
+    assert_close(gsb[2].cpu().numpy(), rgs, TOL, "batched grad_s", blocks=s_blocks(w.net),
+                 floor=lambda: f32()[1])
+    assert_close(lb[2].cpu().numpy(), l4, TOL, "batched loss", blocks=LOSS_BLOCKS,
+                 floor=lambda: f32()[0])
 
 
 def test_adam_step_matches_oracle():
@@ -328,8 +336,11 @@ def test_fastlrnr_build_matches_oracle_at_resolved_rank():
     torch.cuda.synchronize()
     l4, rgs = orc.fast_loss(w.net, ref, w.net.s, w.mu[0].astype(np.float64), w.pts, {},
                             with_grad=True)
-    assert_close(loss.cpu().numpy(), l4, TOL, "fast r8 loss", blocks=LOSS_BLOCKS)
-    assert_close(gs.cpu().numpy(), rgs, TOL, "fast r8 grad_s", blocks=s_blocks(w.net))
+    f32 = fp32(lambda: orc.fast_loss(w.net, ref, w.net.s, w.mu[0], w.pts, {}, with_grad=True))
+    assert_close(loss.cpu().numpy(), l4, TOL, "fast r8 loss", blocks=LOSS_BLOCKS,
+                 floor=lambda: f32()[0])
+    assert_close(gs.cpu().numpy(), rgs, TOL, "fast r8 grad_s", blocks=s_blocks(w.net),
+                 floor=lambda: f32()[1])
     jets = a.forward_jets(fast.net, s, pts.xt_r[:512].contiguous()).cpu().numpy()
     rj = orc.fast_forward_jets(w.net, ref, w.net.s, w.pts.xt_r[:512])
     for c, tol in ((0, TOL), (1, TOL), (2, TOL), (3, TOL_XX)):
@@ -370,9 +381,11 @@ def test_fastlrnr_build_from_perturbed_snapshots_matches_oracle():
     torch.cuda.synchronize()
     l4, rgs = orc.fast_loss(w.net, ops, w.net.s, w.mu[0].astype(np.float64), w.pts, {},
                             with_grad=True)
-    assert_close(loss.cpu().numpy(), l4, TOL, "fast r8 (4 snapshot sets) loss", blocks=LOSS_BLOCKS)
+    f32 = fp32(lambda: orc.fast_loss(w.net, ops, w.net.s, w.mu[0], w.pts, {}, with_grad=True))
+    assert_close(loss.cpu().numpy(), l4, TOL, "fast r8 (4 snapshot sets) loss", blocks=LOSS_BLOCKS,
+                 floor=lambda: f32()[0])
     assert_close(gs.cpu().numpy(), rgs, TOL, "fast r8 (4 snapshot sets) grad_s",
-                 blocks=s_blocks(w.net))
+                 blocks=s_blocks(w.net), floor=lambda: f32()[1])
     fast.close()
 
 
@@ -411,8 +424,11 @@ def test_fastlrnr_qdeim_matches_oracle(n_sets):
     torch.cuda.synchronize()
     l4, rgs = orc.fast_loss(w.net, ops, w.net.s, w.mu[0].astype(np.float64), w.pts, {},
                             with_grad=True)
-    assert_close(loss.cpu().numpy(), l4, TOL, "fast Q-DEIM r8 loss", blocks=LOSS_BLOCKS)
-    assert_close(gs.cpu().numpy(), rgs, TOL, "fast Q-DEIM r8 grad_s", blocks=s_blocks(w.net))
+    f32 = fp32(lambda: orc.fast_loss(w.net, ops, w.net.s, w.mu[0], w.pts, {}, with_grad=True))
+    assert_close(loss.cpu().numpy(), l4, TOL, "fast Q-DEIM r8 loss", blocks=LOSS_BLOCKS,
+                 floor=lambda: f32()[0])
+    assert_close(gs.cpu().numpy(), rgs, TOL, "fast Q-DEIM r8 grad_s", blocks=s_blocks(w.net),
+                 floor=lambda: f32()[1])
     fast.close()
 
 
@@ -454,10 +470,11 @@ def test_fastlrnr_r32_prefix_operators_and_chain():
     torch.cuda.synchronize()
     l4, rgs = orc.fast_loss(w.net, ops, w.net.s, w.mu[0].astype(np.float64), w.pts, {},
                             with_grad=True)
+    f32 = fp32(lambda: orc.fast_loss(w.net, ops, w.net.s, w.mu[0], w.pts, {}, with_grad=True))
     assert_close(loss.cpu().numpy(), l4, TOL, "fast r32 loss (device operators)",
-                 blocks=LOSS_BLOCKS)
+                 blocks=LOSS_BLOCKS, floor=lambda: f32()[0])
     assert_close(gs.cpu().numpy(), rgs, TOL, "fast r32 grad_s (device operators)",
-                 blocks=s_blocks(w.net))
+                 blocks=s_blocks(w.net), floor=lambda: f32()[1])
     fast.close()
 
 
@@ -512,8 +529,11 @@ def test_fastlrnr_reduced_width_below_rank(which, r_hat):
     l4, rgs = orc.fast_loss(w.net, ref, w.net.s, w.mu[0].astype(np.float64), w.pts, {},
                             with_grad=True)
     tag = f"fast {which} r_hat={r_hat}"
-    assert_close(loss.cpu().numpy(), l4, TOL, f"{tag} loss", blocks=LOSS_BLOCKS)
-    assert_close(gs.cpu().numpy(), rgs, TOL, f"{tag} grad_s", blocks=s_blocks(w.net))
+    f32 = fp32(lambda: orc.fast_loss(w.net, ref, w.net.s, w.mu[0], w.pts, {}, with_grad=True))
+    assert_close(loss.cpu().numpy(), l4, TOL, f"{tag} loss", blocks=LOSS_BLOCKS,
+                 floor=lambda: f32()[0])
+    assert_close(gs.cpu().numpy(), rgs, TOL, f"{tag} grad_s", blocks=s_blocks(w.net),
+                 floor=lambda: f32()[1])
     jets = a.forward_jets(fast.net, s, pts.xt_r[:512].contiguous()).cpu().numpy()
     rj = orc.fast_forward_jets(w.net, ref, w.net.s, w.pts.xt_r[:512])
     for c, tol in ((0, TOL), (1, TOL), (2, TOL), (3, TOL_XX)):
