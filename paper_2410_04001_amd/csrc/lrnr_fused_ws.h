@@ -1218,6 +1218,11 @@ hipError_t launch_grad_ws(const KNet& net, const KInst& inst, const KGrid& grid,
   bool ws = false;
   if constexpr (RP <= kWsMaxRP) ws = four_role<RP>(grid.Wmax_p);
   if (!ws) {
+    if constexpr (RP <= 8) {
+      // a wave that meets |a| > kFastRange redoes that layer pass with
+      // ocml's sin/cos at once: no relaunch of flagged workgroups
+      return launch_one<RP, MODE_GRAD, SC_REDO>(net, inst, grid, stream);
+    }
     hipError_t e = launch_one<RP, MODE_GRAD, SC_TRACK>(net, inst, grid, stream);
     if (e != hipSuccess) return e;
     return launch_one<RP, MODE_GRAD, SC_ACC>(net, inst, grid, stream);

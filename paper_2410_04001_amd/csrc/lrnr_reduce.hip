@@ -80,9 +80,69 @@ __global__ void reduce_stage2(KReduce kr) {
   }
 }
 
+// Both stages in one launch when an instance has at most kRedFusedChunks
+// chunks: thread (ex, c) of a block forms the stage-1 sum of chunk c for
+// element blockIdx.x * kRedFusedElems + ex, and thread (ex, 0) then adds the
+// chunk sums in chunk order.  The additions and their order are those of
+// reduce_stage1 + reduce_stage2, so the results are the same bits.
+constexpr int kRedFusedElems = 8;
+constexpr int kRedFusedChunks = 32;
+
+__global__ __launch_bounds__(kRedFusedElems* kRedFusedChunks) void reduce_fused(KReduce kr) {
+  __shared__ double part[kRedFusedElems][kRedFusedChunks];
+  __shared__ double col[kRedFusedElems];
+  const int ex = threadIdx.x / kRedFusedChunks, c = threadIdx.x % kRedFusedChunks;
+  const int e = blockIdx.x * kRedFusedElems + ex, inst = blockIdx.y;
+  const int P = kr.P;
+  if (e < kr.E && c < kr.nchunk) {
+    const int r0 = c * kRedChunk, r1 = min(kr.G_inst, r0 + kRedChunk);
+    const float* base = kr.partials + ((int64_t)inst * kr.G_inst + r0) * P + e;
+    part[ex][c] = ordered_sum(base, P, r1 - r0);
+  }
+  __syncthreads();
+  if (c == 0) {
+    double acc = 0.0;
+    for (int k = 0; k < kr.nchunk; ++k) acc += part[ex][k];
+    col[ex] = acc;
+  }
+  __syncthreads();
+  if (c != 0 || e >= kr.E) return;
+  const float* s = kr.s + inst * kr.s_stride;
+  const float* sref = kr.s_ref ? kr.s_ref + inst * kr.s_stride : nullptr;
+  const bool loc = kr.lambda_loc != 0.f && sref != nullptr;
+  if (e == 0 && kr.loss) {
+    // elements 0, 1, 2 of the record are in this block (kRedFusedElems >= 3)
+    const double ti = kr.n_r ? (double)kr.w_r / kr.n_r * col[0] : 0.0;
+    const double t0 = kr.n_0 ? (double)kr.w_0 / kr.n_0 * col[1] : 0.0;
+    const double tb = kr.n_b ? (double)kr.w_b / kr.n_b * col[2] : 0.0;
+    double tl = 0.0;
+    if (loc)
+      for (int k = 0; k < kr.r_total; ++k) tl += fabs((double)s[k] - (double)sref[k]);
+    float* out = kr.loss + 4 * inst;
+    out[0] = (float)(ti + t0 + tb + (double)kr.lambda_loc * tl);
+    out[1] = (float)ti;
+    out[2] = (float)t0;
+    out[3] = (float)tb;
+  }
+  if (e >= 4 && e < 4 + kr.r_total && kr.grad_s) {
+    const int k = e - 4;
+    double g = col[ex];
+    if (loc) g += (double)kr.lambda_loc * sgn(s[k] - sref[k]);
+    kr.grad_s[(int64_t)inst * kr.r_total + k] = (float)g;
+  }
+  if (e >= 4 + kr.r_total && e < 4 + kr.r_total + kr.b_total && kr.grad_b && inst == 0)
+    kr.grad_b[e - 4 - kr.r_total] = (float)col[ex];
+}
+
 hipError_t launch_reduce(const KReduce& kr, hipStream_t stream) {
   const int bx = 256;
   const int gx = (kr.E + bx - 1) / bx;
+  if (kr.nchunk > 0 && kr.nchunk <= kRedFusedChunks) {
+    const int gf = (kr.E + kRedFusedElems - 1) / kRedFusedElems;
+    hipLaunchKernelGGL(reduce_fused, dim3(gf, kr.B), dim3(kRedFusedElems * kRedFusedChunks), 0,
+                       stream, kr);
+    return hipGetLastError();
+  }
   if (kr.nchunk > 0) {
     hipLaunchKernelGGL(reduce_stage1, dim3(gx, kr.nchunk, kr.B), dim3(bx), 0, stream,
                        kr.partials, kr.red1, kr.G_inst, kr.P, kr.E, kr.nchunk);
