@@ -204,7 +204,7 @@ __device__ void basis_workgroup(const KBasis& kb, const KTile& tile, float* __re
     stage_layer<kThreads>(net, s, l, KI, KO, sm.Us, sm.Vs, sm.bs, sm.ss);
     __syncthreads();
     const int Wp = (net.M[l] + 3) & ~3;
-    fwd_dispatch<NJ, RGM, SC_REDO>(first, last, sm, Wp, li, y, yo, amax);
+    fwd_dispatch<NJ, RGM, SC_REDO, true>(first, last, sm, Wp, li, y, yo, amax);
     if (!last) ckpt_store<NJ, RGM>(ckbase + (l - 1) * kSlot, lane, yo);
 #pragma unroll
     for (int c = 0; c < NJ; ++c)

@@ -311,11 +311,15 @@ __device__ __forceinline__ void sigma_bwd(const f4 (&a)[NJ], const f4 (&zb)[NJ],
 
 // ---------------------------------------------------------------------------
 // One hidden layer, forward: ys = s * y (in place), yo = V^T sin-jets(U ys + b).
-// The loop is software-pipelined: the U-side MFMAs of the next neuron group
-// are issued next to the VALU sin-jet work of the current one.  Returns the
-// largest |a_v| seen (to select the accurate sin/cos path if needed).
+// With PIPE the loop is software-pipelined: the U-side MFMAs of the next
+// neuron group are issued next to the VALU sin-jet work of the current one.
+// That pays in the reverse-mode kernels (two waves per SIMD, where the
+// forward sweep is not the register peak); the forward-only kernels run
+// three waves per SIMD, where the extra accumulators only add spills.
+// Returns the largest |a_v| seen (to select the accurate sin/cos path if
+// needed).
 // ---------------------------------------------------------------------------
-template <int NJ, int RGM, int RGI, int RGO, bool ACC>
+template <int NJ, int RGM, int RGI, int RGO, bool ACC, bool PIPE>
 __device__ __forceinline__ float layer_fwd_pass(const float* __restrict__ Us,
                                                 const float* __restrict__ Vs,
                                                 const float* __restrict__ bs, int Wp, int li,
@@ -326,6 +330,14 @@ __device__ __forceinline__ float layer_fwd_pass(const float* __restrict__ Us,
     for (int g = 0; g < RGO; ++g) yo[c][g] = zero4();
   float amax = 0.f;
   f4 a[NJ], z[NJ];
+  if constexpr (!PIPE) {
+    for (int w0 = 0; w0 < Wp; w0 += 4) {
+      u_side<NJ, RGM, RGI>(Us, bs, w0, li, ys, a);
+      sigma_fwd<NJ, ACC>(a, z, amax);
+      v_side<NJ, RGM, RGO>(Vs, w0, li, z, yo);
+    }
+    return amax;
+  }
   u_side<NJ, RGM, RGI>(Us, bs, 0, li, ys, a);
   for (int w0 = 0; w0 < Wp - 4; w0 += 4) {
     f4 an[NJ];
@@ -341,7 +353,7 @@ __device__ __forceinline__ float layer_fwd_pass(const float* __restrict__ Us,
   return amax;
 }
 
-template <int NJ, int RGM, int RGI, int RGO, int SC>
+template <int NJ, int RGM, int RGI, int RGO, int SC, bool PIPE>
 __device__ __forceinline__ void layer_fwd(const float* __restrict__ Us,
                                           const float* __restrict__ Vs,
                                           const float* __restrict__ bs,
@@ -354,13 +366,13 @@ __device__ __forceinline__ void layer_fwd(const float* __restrict__ Us,
     for (int c = 0; c < NJ; ++c) y[c][g] *= s4;
   }
   if constexpr (SC == SC_ACC) {
-    layer_fwd_pass<NJ, RGM, RGI, RGO, true>(Us, Vs, bs, Wp, li, y, yo);
+    layer_fwd_pass<NJ, RGM, RGI, RGO, true, PIPE>(Us, Vs, bs, Wp, li, y, yo);
   } else {
-    const float m = layer_fwd_pass<NJ, RGM, RGI, RGO, false>(Us, Vs, bs, Wp, li, y, yo);
+    const float m = layer_fwd_pass<NJ, RGM, RGI, RGO, false, PIPE>(Us, Vs, bs, Wp, li, y, yo);
     amax = fmaxf(amax, m);
     if constexpr (SC == SC_REDO) {
       if (__builtin_expect(__any(!(m <= kFastRange)), 0))
-        layer_fwd_pass<NJ, RGM, RGI, RGO, true>(Us, Vs, bs, Wp, li, y, yo);
+        layer_fwd_pass<NJ, RGM, RGI, RGO, true, PIPE>(Us, Vs, bs, Wp, li, y, yo);
     }
   }
 }
@@ -369,8 +381,9 @@ __device__ __forceinline__ void layer_fwd(const float* __restrict__ Us,
 // One hidden layer, reverse: recompute a = U (s*y) + b, pull yb = dL/dy^{l+1}
 // back through V and the sin jets, write the layer's dL/db row, and return
 // wb = U^T abar (so that dL/ds = sum_c wb * y and dL/dy^l = s * wb).  The
-// U-side and V-side MFMAs of the next group overlap the current group's VALU
-// adjoint work.
+// loop is not software-pipelined: carrying the next group's a and zb beside
+// the current ones spilled at the two-waves-per-SIMD register budget and
+// measured 3-7 % slower than this plain loop.
 // ---------------------------------------------------------------------------
 template <int NJ, int RGM, int RGI, int RGO, bool ACC>
 __device__ __forceinline__ float layer_bwd_pass(const float* __restrict__ Us,
@@ -386,27 +399,14 @@ __device__ __forceinline__ float layer_bwd_pass(const float* __restrict__ Us,
   const int comp = sum4_component(lane);
   float amax = 0.f;
   f4 a[NJ], zb[NJ], ab[NJ];
-  u_side<NJ, RGM, RGI>(Us, bs, 0, li, ys, a);
-  v_rev<NJ, RGM, RGO>(Vs, 0, li, yb, zb);
-  for (int w0 = 0; w0 < Wp - 4; w0 += 4) {
-    f4 an[NJ], zbn[NJ];
-    u_side<NJ, RGM, RGI>(Us, bs, w0 + 4, li, ys, an);
-    v_rev<NJ, RGM, RGO>(Vs, w0 + 4, li, yb, zbn);
+  for (int w0 = 0; w0 < Wp; w0 += 4) {
+    u_side<NJ, RGM, RGI>(Us, bs, w0, li, ys, a);
+    v_rev<NJ, RGM, RGO>(Vs, w0, li, yb, zb);
     sigma_bwd<NJ, ACC>(a, zb, ab, amax);
     const float bsum = wave_sum4(ab[0], lane);
     if ((lane & 15) == 0) bbar_row[w0 + comp] = bsum;
     ut_side<NJ, RGM, RGI>(Us, w0, li, ab, wb);
-#pragma unroll
-    for (int c = 0; c < NJ; ++c) {
-      a[c] = an[c];
-      zb[c] = zbn[c];
-    }
-    interleave<NJ * 4 * (RGI + RGO)>();
   }
-  sigma_bwd<NJ, ACC>(a, zb, ab, amax);
-  const float bsum = wave_sum4(ab[0], lane);
-  if ((lane & 15) == 0) bbar_row[Wp - 4 + comp] = bsum;
-  ut_side<NJ, RGM, RGI>(Us, Wp - 4, li, ab, wb);
   return amax;
 }
 
@@ -521,18 +521,18 @@ __device__ __forceinline__ void input_jets(const KNet& net, float x, float t,
   }
 }
 
-template <int NJ, int RGM, int SC>
+template <int NJ, int RGM, int SC, bool PIPE>
 __device__ __forceinline__ void fwd_dispatch(bool first, bool last, const Smem& sm, int Wp,
                                              int li, f4 (&y)[NJ][RGM],
                                              f4 (&yo)[NJ][RGM], float& amax) {
   if (first && last)
-    layer_fwd<NJ, RGM, 1, 1, SC>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
+    layer_fwd<NJ, RGM, 1, 1, SC, PIPE>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
   else if (first)
-    layer_fwd<NJ, RGM, 1, RGM, SC>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
+    layer_fwd<NJ, RGM, 1, RGM, SC, PIPE>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
   else if (last)
-    layer_fwd<NJ, RGM, RGM, 1, SC>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
+    layer_fwd<NJ, RGM, RGM, 1, SC, PIPE>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
   else
-    layer_fwd<NJ, RGM, RGM, RGM, SC>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
+    layer_fwd<NJ, RGM, RGM, RGM, SC, PIPE>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
 }
 
 template <int NJ, int RGM, int SC>
@@ -621,7 +621,7 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, int64_t ckpt_p
     stage_layer<kThreads>(net, s, l, KI, KO, sm.Us, sm.Vs, sm.bs, sm.ss);
     __syncthreads();
     const int Wp = (net.M[l] + 3) & ~3;
-    fwd_dispatch<NJ, RGM, SC>(first, last, sm, Wp, li, y, yo, amax);
+    fwd_dispatch<NJ, RGM, SC, REV>(first, last, sm, Wp, li, y, yo, amax);
     if constexpr (REV)
       if (!last) ckpt_store<NJ, RGM>(ckbase + (l - 1) * kSlot, lane, yo);
 #pragma unroll
