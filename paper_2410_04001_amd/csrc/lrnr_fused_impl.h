@@ -138,10 +138,23 @@ __device__ __forceinline__ int sum4_component(int lane) {
 // any of its MFMAs issue, so that only the first read's latency is exposed
 // (reading them one by one between MFMA batches stalls the wave on each).
 
+// Position of a hidden layer in the chain, as flags.  The first hidden layer
+// reads y^1 = V^1T (x, t): its rank is at most 2 (the input width), so the
+// U-side contraction needs two of the tile's four k, and its d2/dx2 jet is
+// zero, so a_xx = 0 and that jet's U^T adjoint is never used (ds^1 weights
+// it by y^1_xx = 0, and nothing is propagated below the first layer).  The
+// last hidden layer's V side has rank r_L = 1 (a scalar output): one column
+// of the 4-wide tile, contracted on the VALU instead of by MFMAs that would
+// be three quarters padding.
+constexpr int kEdgeFirst = 1, kEdgeLast = 2;
+
 // a_c = U[w0..w0+3] (s*y_c) (+ b for the value jet)
-template <int NJ, int RGM, int RGI>
+template <int NJ, int RGM, int RGI, int EDGE = 0>
 __device__ __forceinline__ void u_side(const float* __restrict__ Us, const float* __restrict__ bs,
                                        int w0, int li, const f4 (&y)[NJ][RGM], f4 (&a)[NJ]) {
+  constexpr bool FIRST = EDGE & kEdgeFirst;
+  constexpr int KK = FIRST ? 2 : 4;
+  constexpr int NJM = FIRST && NJ == 4 ? 3 : NJ;
   constexpr int KI = 4 * RGI;
   const float* urow = Us + (w0 + li) * KI;
   f4 u4[RGI];
@@ -153,16 +166,30 @@ __device__ __forceinline__ void u_side(const float* __restrict__ Us, const float
 #pragma unroll
   for (int g = 0; g < RGI; ++g)
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
+    for (int kk = 0; kk < KK; ++kk)
 #pragma unroll
-      for (int c = 0; c < NJ; ++c) a[c] = mfma4(u4[g][kk], y[c][g][kk], a[c]);
+      for (int c = 0; c < NJM; ++c) a[c] = mfma4(u4[g][kk], y[c][g][kk], a[c]);
 }
 
 // yo_c += V[w0..w0+3]^T z_c
-template <int NJ, int RGM, int RGO>
+template <int NJ, int RGM, int RGO, int EDGE = 0>
 __device__ __forceinline__ void v_side(const float* __restrict__ Vs, int w0, int li,
                                        const f4 (&z)[NJ], f4 (&yo)[NJ][RGM]) {
   constexpr int KO = 4 * RGO;
+  if constexpr ((EDGE & kEdgeLast) != 0) {
+    // rank 1: yo_c[0] += sum_j V[w0+j][0] z_c[j]
+    float v0[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v0[j] = Vs[(w0 + j) * KO];
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) {
+      float acc = yo[c][0][0];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc = __builtin_fmaf(v0[j], z[c][j], acc);
+      yo[c][0][0] = acc;
+    }
+    return;
+  }
   float v[4][RGO];
 #pragma unroll
   for (int j = 0; j < 4; ++j)
@@ -177,10 +204,19 @@ __device__ __forceinline__ void v_side(const float* __restrict__ Vs, int w0, int
 }
 
 // zb_c = V[w0..w0+3] yb_c
-template <int NJ, int RGM, int RGO>
+template <int NJ, int RGM, int RGO, int EDGE = 0>
 __device__ __forceinline__ void v_rev(const float* __restrict__ Vs, int w0, int li,
                                       const f4 (&yb)[NJ][RGM], f4 (&zb)[NJ]) {
   constexpr int KO = 4 * RGO;
+  if constexpr ((EDGE & kEdgeLast) != 0) {
+    // rank 1: zb_c[j] = V[w0+j][0] yb_c[0]
+    f4 v0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v0[j] = Vs[(w0 + j) * KO];
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) zb[c] = v0 * yb[c][0][0];
+    return;
+  }
   const float* vrow = Vs + (w0 + li) * KO;
   f4 v4[RGO];
 #pragma unroll
@@ -195,10 +231,11 @@ __device__ __forceinline__ void v_rev(const float* __restrict__ Vs, int w0, int 
       for (int c = 0; c < NJ; ++c) zb[c] = mfma4(v4[g][kk], yb[c][g][kk], zb[c]);
 }
 
-// wb_c += U[w0..w0+3]^T ab_c
-template <int NJ, int RGM, int RGI>
+// wb_c += U[w0..w0+3]^T ab_c (the first layer leaves wb_xx at its zero start)
+template <int NJ, int RGM, int RGI, int EDGE = 0>
 __device__ __forceinline__ void ut_side(const float* __restrict__ Us, int w0, int li,
                                         const f4 (&ab)[NJ], f4 (&wb)[NJ][RGM]) {
+  constexpr int NJM = (EDGE & kEdgeFirst) && NJ == 4 ? 3 : NJ;
   constexpr int KI = 4 * RGI;
   float u[4][RGI];
 #pragma unroll
@@ -210,7 +247,7 @@ __device__ __forceinline__ void ut_side(const float* __restrict__ Us, int w0, in
 #pragma unroll
     for (int g = 0; g < RGI; ++g)
 #pragma unroll
-      for (int c = 0; c < NJ; ++c) wb[c][g] = mfma4(u[j][g], ab[c][j], wb[c][g]);
+      for (int c = 0; c < NJM; ++c) wb[c][g] = mfma4(u[j][g], ab[c][j], wb[c][g]);
 }
 
 // Scheduling hint for a pipelined loop body whose first NM MFMAs do not depend
@@ -319,7 +356,7 @@ __device__ __forceinline__ void sigma_bwd(const f4 (&a)[NJ], const f4 (&zb)[NJ],
 // Returns the largest |a_v| seen (to select the accurate sin/cos path if
 // needed).
 // ---------------------------------------------------------------------------
-template <int NJ, int RGM, int RGI, int RGO, bool ACC, bool PIPE>
+template <int NJ, int RGM, int RGI, int RGO, bool ACC, bool PIPE, int EDGE>
 __device__ __forceinline__ float layer_fwd_pass(const float* __restrict__ Us,
                                                 const float* __restrict__ Vs,
                                                 const float* __restrict__ bs, int Wp, int li,
@@ -332,28 +369,28 @@ __device__ __forceinline__ float layer_fwd_pass(const float* __restrict__ Us,
   f4 a[NJ], z[NJ];
   if constexpr (!PIPE) {
     for (int w0 = 0; w0 < Wp; w0 += 4) {
-      u_side<NJ, RGM, RGI>(Us, bs, w0, li, ys, a);
+      u_side<NJ, RGM, RGI, EDGE>(Us, bs, w0, li, ys, a);
       sigma_fwd<NJ, ACC>(a, z, amax);
-      v_side<NJ, RGM, RGO>(Vs, w0, li, z, yo);
+      v_side<NJ, RGM, RGO, EDGE>(Vs, w0, li, z, yo);
     }
     return amax;
   }
-  u_side<NJ, RGM, RGI>(Us, bs, 0, li, ys, a);
+  u_side<NJ, RGM, RGI, EDGE>(Us, bs, 0, li, ys, a);
   for (int w0 = 0; w0 < Wp - 4; w0 += 4) {
     f4 an[NJ];
-    u_side<NJ, RGM, RGI>(Us, bs, w0 + 4, li, ys, an);
+    u_side<NJ, RGM, RGI, EDGE>(Us, bs, w0 + 4, li, ys, an);
     sigma_fwd<NJ, ACC>(a, z, amax);
-    v_side<NJ, RGM, RGO>(Vs, w0, li, z, yo);
+    v_side<NJ, RGM, RGO, EDGE>(Vs, w0, li, z, yo);
 #pragma unroll
     for (int c = 0; c < NJ; ++c) a[c] = an[c];
     interleave<NJ * 4 * RGI>();
   }
   sigma_fwd<NJ, ACC>(a, z, amax);
-  v_side<NJ, RGM, RGO>(Vs, Wp - 4, li, z, yo);
+  v_side<NJ, RGM, RGO, EDGE>(Vs, Wp - 4, li, z, yo);
   return amax;
 }
 
-template <int NJ, int RGM, int RGI, int RGO, int SC, bool PIPE>
+template <int NJ, int RGM, int RGI, int RGO, int SC, bool PIPE, int EDGE>
 __device__ __forceinline__ void layer_fwd(const float* __restrict__ Us,
                                           const float* __restrict__ Vs,
                                           const float* __restrict__ bs,
@@ -366,13 +403,13 @@ __device__ __forceinline__ void layer_fwd(const float* __restrict__ Us,
     for (int c = 0; c < NJ; ++c) y[c][g] *= s4;
   }
   if constexpr (SC == SC_ACC) {
-    layer_fwd_pass<NJ, RGM, RGI, RGO, true, PIPE>(Us, Vs, bs, Wp, li, y, yo);
+    layer_fwd_pass<NJ, RGM, RGI, RGO, true, PIPE, EDGE>(Us, Vs, bs, Wp, li, y, yo);
   } else {
-    const float m = layer_fwd_pass<NJ, RGM, RGI, RGO, false, PIPE>(Us, Vs, bs, Wp, li, y, yo);
+    const float m = layer_fwd_pass<NJ, RGM, RGI, RGO, false, PIPE, EDGE>(Us, Vs, bs, Wp, li, y, yo);
     amax = fmaxf(amax, m);
     if constexpr (SC == SC_REDO) {
       if (__builtin_expect(__any(!(m <= kFastRange)), 0))
-        layer_fwd_pass<NJ, RGM, RGI, RGO, true, PIPE>(Us, Vs, bs, Wp, li, y, yo);
+        layer_fwd_pass<NJ, RGM, RGI, RGO, true, PIPE, EDGE>(Us, Vs, bs, Wp, li, y, yo);
     }
   }
 }
@@ -385,7 +422,7 @@ __device__ __forceinline__ void layer_fwd(const float* __restrict__ Us,
 // the current ones spilled at the two-waves-per-SIMD register budget and
 // measured 3-7 % slower than this plain loop.
 // ---------------------------------------------------------------------------
-template <int NJ, int RGM, int RGI, int RGO, bool ACC>
+template <int NJ, int RGM, int RGI, int RGO, bool ACC, int EDGE>
 __device__ __forceinline__ float layer_bwd_pass(const float* __restrict__ Us,
                                                 const float* __restrict__ Vs,
                                                 const float* __restrict__ bs, int Wp, int li,
@@ -400,17 +437,17 @@ __device__ __forceinline__ float layer_bwd_pass(const float* __restrict__ Us,
   float amax = 0.f;
   f4 a[NJ], zb[NJ], ab[NJ];
   for (int w0 = 0; w0 < Wp; w0 += 4) {
-    u_side<NJ, RGM, RGI>(Us, bs, w0, li, ys, a);
-    v_rev<NJ, RGM, RGO>(Vs, w0, li, yb, zb);
+    u_side<NJ, RGM, RGI, EDGE>(Us, bs, w0, li, ys, a);
+    v_rev<NJ, RGM, RGO, EDGE>(Vs, w0, li, yb, zb);
     sigma_bwd<NJ, ACC>(a, zb, ab, amax);
     const float bsum = wave_sum4(ab[0], lane);
     if ((lane & 15) == 0) bbar_row[w0 + comp] = bsum;
-    ut_side<NJ, RGM, RGI>(Us, w0, li, ab, wb);
+    ut_side<NJ, RGM, RGI, EDGE>(Us, w0, li, ab, wb);
   }
   return amax;
 }
 
-template <int NJ, int RGM, int RGI, int RGO, int SC>
+template <int NJ, int RGM, int RGI, int RGO, int SC, int EDGE>
 __device__ __forceinline__ void layer_bwd(const float* __restrict__ Us,
                                           const float* __restrict__ Vs,
                                           const float* __restrict__ bs,
@@ -425,14 +462,14 @@ __device__ __forceinline__ void layer_bwd(const float* __restrict__ Us,
     for (int c = 0; c < NJ; ++c) y[c][g] *= s4;
   }
   if constexpr (SC == SC_ACC) {
-    layer_bwd_pass<NJ, RGM, RGI, RGO, true>(Us, Vs, bs, Wp, li, lane, y, yb, wb, bbar_row);
+    layer_bwd_pass<NJ, RGM, RGI, RGO, true, EDGE>(Us, Vs, bs, Wp, li, lane, y, yb, wb, bbar_row);
   } else {
     const float m =
-        layer_bwd_pass<NJ, RGM, RGI, RGO, false>(Us, Vs, bs, Wp, li, lane, y, yb, wb, bbar_row);
+        layer_bwd_pass<NJ, RGM, RGI, RGO, false, EDGE>(Us, Vs, bs, Wp, li, lane, y, yb, wb, bbar_row);
     amax = fmaxf(amax, m);
     if constexpr (SC == SC_REDO) {
       if (__builtin_expect(__any(!(m <= kFastRange)), 0))
-        layer_bwd_pass<NJ, RGM, RGI, RGO, true>(Us, Vs, bs, Wp, li, lane, y, yb, wb, bbar_row);
+        layer_bwd_pass<NJ, RGM, RGI, RGO, true, EDGE>(Us, Vs, bs, Wp, li, lane, y, yb, wb, bbar_row);
     }
   }
 }
@@ -525,14 +562,15 @@ template <int NJ, int RGM, int SC, bool PIPE>
 __device__ __forceinline__ void fwd_dispatch(bool first, bool last, const Smem& sm, int Wp,
                                              int li, f4 (&y)[NJ][RGM],
                                              f4 (&yo)[NJ][RGM], float& amax) {
+  constexpr int F = kEdgeFirst, LA = kEdgeLast;
   if (first && last)
-    layer_fwd<NJ, RGM, 1, 1, SC, PIPE>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
+    layer_fwd<NJ, RGM, 1, 1, SC, PIPE, F | LA>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
   else if (first)
-    layer_fwd<NJ, RGM, 1, RGM, SC, PIPE>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
+    layer_fwd<NJ, RGM, 1, RGM, SC, PIPE, F>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
   else if (last)
-    layer_fwd<NJ, RGM, RGM, 1, SC, PIPE>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
+    layer_fwd<NJ, RGM, RGM, 1, SC, PIPE, LA>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
   else
-    layer_fwd<NJ, RGM, RGM, RGM, SC, PIPE>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
+    layer_fwd<NJ, RGM, RGM, RGM, SC, PIPE, 0>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
 }
 
 template <int NJ, int RGM, int SC>
@@ -540,18 +578,19 @@ __device__ __forceinline__ void bwd_dispatch(bool first, bool last, const Smem& 
                                              int li, int lane, f4 (&y)[NJ][RGM],
                                              const f4 (&yb)[NJ][RGM], f4 (&wb)[NJ][RGM],
                                              float* bbar_row, float& amax) {
+  constexpr int F = kEdgeFirst, LA = kEdgeLast;
   if (first && last)
-    layer_bwd<NJ, RGM, 1, 1, SC>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb, bbar_row,
-                                 amax);
+    layer_bwd<NJ, RGM, 1, 1, SC, F | LA>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb,
+                                         bbar_row, amax);
   else if (first)
-    layer_bwd<NJ, RGM, 1, RGM, SC>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb,
-                                   bbar_row, amax);
+    layer_bwd<NJ, RGM, 1, RGM, SC, F>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb,
+                                      bbar_row, amax);
   else if (last)
-    layer_bwd<NJ, RGM, RGM, 1, SC>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb,
-                                   bbar_row, amax);
+    layer_bwd<NJ, RGM, RGM, 1, SC, LA>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb,
+                                       bbar_row, amax);
   else
-    layer_bwd<NJ, RGM, RGM, RGM, SC>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb,
-                                     bbar_row, amax);
+    layer_bwd<NJ, RGM, RGM, RGM, SC, 0>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb,
+                                        bbar_row, amax);
 }
 
 template <int NJ, int RGM>
