@@ -143,6 +143,7 @@ Plan make_plan(const KNet& k, int RP, int Wmax_p, const lrnr_points* pts, int B,
   g.B = B;
   g.P = record_floats(k);
   g.Wmax_p = Wmax_p;
+  g.res_layers = resident_layers(RP, Wmax_p, k.L);
   g.s_stride = k.r_total;
   // (L-1) slots per 64-point tile: y^2..y^{L-1} in the forward sweep, then
   // ybar^2..ybar^{L-1} on their way down in the reverse sweep

@@ -326,6 +326,7 @@ __attribute__((amdgpu_waves_per_eu(basis_waves_per_simd<RP>()))) void lrnr_basis
   sm.bbar = nullptr;
   sm.sbar = nullptr;
   sm.lw = nullptr;
+  sm.lstride = 0;
   const int inst_id = blockIdx.x / grid.G_inst;
   int wg = blockIdx.x - inst_id * grid.G_inst;
   int kind = 0;
@@ -342,6 +343,7 @@ __attribute__((amdgpu_waves_per_eu(basis_waves_per_simd<RP>()))) void lrnr_basis
   tile.rec = nullptr;
   tile.ck = grid.ckpt + (int64_t)blockIdx.x * kWaves * grid.ckpt_per_wave;
   tile.flag = nullptr;
+  tile.stage_net = true;
   float* wrec = kb.wrec + ((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * kb.PB;
   if (kind == 0)
     basis_workgroup<RP, 4>(kb, tile, wrec, kind, wg, s, mu, sm);

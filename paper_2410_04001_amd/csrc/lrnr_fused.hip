@@ -1,5 +1,7 @@
 // Dispatch of the fused kernel over the compiled rank tiles; the kernel body is
 // in lrnr_fused_impl.h and each tile is instantiated in its own source file.
+#include <algorithm>
+
 #include "lrnr_internal.h"
 
 namespace lrnr {
@@ -12,10 +14,23 @@ hipError_t launch_table_rp(int mode, const KTableGrid& tg, int grid, hipStream_t
 template <int RP>
 int table_grid_rp(int mode, int Wmax_p);
 
-size_t fused_lds_bytes(int RP, int Wmax_p) {
-  const size_t floats = (size_t)Wmax_p * RP * 2 + Wmax_p + RP + (size_t)kWaves * Wmax_p +
-                        (size_t)kWaves * RP + kWaves * 4;
+size_t fused_lds_bytes(int RP, int Wmax_p, int n_slabs) {
+  const size_t n = (size_t)std::max(1, n_slabs);
+  const size_t floats = n * ((size_t)Wmax_p * RP * 2 + Wmax_p + RP) +
+                        n * kWaves * ((size_t)Wmax_p + RP) + kWaves * 5;
   return floats * sizeof(float);
+}
+
+// Resident layers are worth it where a tile is short (narrow layers, small
+// ranks): the per-layer staging costs two or three workgroup barriers per
+// layer and sweep.  The budget keeps three workgroups per CU within the
+// 160 KB of LDS, so occupancy stays register-bound.
+constexpr size_t kResidentLdsMax = 48 * 1024;
+
+int resident_layers(int RP, int Wmax_p, int L) {
+  const int n = L - 1;
+  if (n < 1 || fused_lds_bytes(RP, Wmax_p, n) > kResidentLdsMax) return 0;
+  return n;
 }
 
 int padded_rank(int rmax) {

@@ -477,15 +477,50 @@ __device__ __forceinline__ void layer_bwd(const float* __restrict__ Us,
 // ---------------------------------------------------------------------------
 // Workgroup driver
 // ---------------------------------------------------------------------------
+// LDS of a workgroup.  Per layer slab: U [Wmax_p][RP], V [Wmax_p][RP],
+// b [Wmax_p], s [RP]; then per slab the waves' b and s gradient rows.  With
+// one slab (lstride == 0) the layers are staged one at a time; with resident
+// layers, hidden layer l lives in slab l - 1, lstride floats apart, for the
+// whole tile.
 struct Smem {
   float* Us;
   float* Vs;
   float* bs;
   float* ss;
-  float* bbar;   // [kWaves][Wmax_p]
-  float* sbar;   // [kWaves][RP]
-  float* lw;     // [kWaves][4]
+  float* bbar;   // [slabs][kWaves][Wmax_p]
+  float* sbar;   // [slabs][kWaves][RP]
+  float* lw;     // [kWaves][4] wave sums, then [kWaves] range flags
+  int lstride;   // floats between layer slabs; 0: one slab
 };
+
+__device__ __forceinline__ Smem make_smem(float* base, int Wm, int RP, int n_slabs) {
+  const int n = n_slabs > 0 ? n_slabs : 1;
+  const int slab = Wm * RP * 2 + Wm + RP;
+  Smem sm;
+  sm.Us = base;
+  sm.Vs = sm.Us + Wm * RP;
+  sm.bs = sm.Vs + Wm * RP;
+  sm.ss = sm.bs + Wm;
+  sm.bbar = base + n * slab;
+  sm.sbar = sm.bbar + n * kWaves * Wm;
+  sm.lw = sm.sbar + n * kWaves * RP;
+  sm.lstride = n_slabs > 0 ? slab : 0;
+  return sm;
+}
+
+// The slab of hidden layer l (the one slab when layers are staged in turn).
+__device__ __forceinline__ Smem layer_smem(const Smem& sm, int l, int Wm, int RP) {
+  if (sm.lstride == 0) return sm;
+  Smem v = sm;
+  const int o = (l - 1) * sm.lstride;
+  v.Us += o;
+  v.Vs += o;
+  v.bs += o;
+  v.ss += o;
+  v.bbar += (l - 1) * kWaves * Wm;
+  v.sbar += (l - 1) * kWaves * RP;
+  return v;
+}
 
 // dst[i] = src[i] for i < n (float4), two loads in flight per thread.
 template <int NT>
@@ -536,6 +571,24 @@ __device__ void stage_layer(const KNet& net, const float* __restrict__ s, int l,
   for (int i = tx; i < Wp; i += NT) bs[i] = i < W ? b[i] : 0.f;
   if (ss)
     for (int i = tx; i < KI; i += NT) ss[i] = i < rl ? s[net.offS[l] + i] : 0.f;
+}
+
+// Resident layers: stage every hidden layer's slab (or, when the factors are
+// already there from the previous tile of the same net, only s).
+template <int RP>
+__device__ void stage_resident(const KNet& net, const float* __restrict__ s, bool factors,
+                               const Smem& sm, int Wm) {
+  const int L = net.L, tx = threadIdx.x;
+  for (int l = 1; l <= L - 1; ++l) {
+    const int KI = l == 1 ? 4 : RP, KO = l == L - 1 ? 4 : RP;
+    const Smem ls = layer_smem(sm, l, Wm, RP);
+    if (factors) {
+      stage_layer<kThreads>(net, s, l, KI, KO, ls.Us, ls.Vs, ls.bs, ls.ss);
+    } else {
+      const int rl = net.r[l];
+      for (int i = tx; i < KI; i += kThreads) ls.ss[i] = i < rl ? s[net.offS[l] + i] : 0.f;
+    }
+  }
 }
 
 // Jets of y^1 = V^1T (x, t): value V^1T (x,t), d/dx row 0 of V^1, d/dt row 1,
@@ -650,17 +703,27 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, int64_t ckpt_p
   constexpr int64_t kSlot = 4 * RGM * 64 * 4;  // floats per checkpointed layer
 
   // ---- forward sweep ------------------------------------------------------
+  // Resident layers: one staging and one barrier for the whole tile (the
+  // caller's LDS is free on entry); otherwise two barriers per layer.
+  const bool res = sm.lstride != 0;
+  if (res) {
+    stage_resident<RP>(net, s, tile.stage_net, sm, Wmax_p);
+    __syncthreads();
+  }
   float amax = 0.f;  // largest |a| met by this lane (sin/cos range check)
   f4 y[NJ][RGM], yo[NJ][RGM];
   input_jets<NJ, RGM>(net, x, t, y);
   for (int l = 1; l <= L - 1; ++l) {
     const bool first = l == 1, last = l == L - 1;
     const int KI = first ? 4 : RP, KO = last ? 4 : RP;
-    __syncthreads();
-    stage_layer<kThreads>(net, s, l, KI, KO, sm.Us, sm.Vs, sm.bs, sm.ss);
-    __syncthreads();
+    const Smem ls = layer_smem(sm, l, Wmax_p, RP);
+    if (!res) {
+      __syncthreads();
+      stage_layer<kThreads>(net, s, l, KI, KO, sm.Us, sm.Vs, sm.bs, sm.ss);
+      __syncthreads();
+    }
     const int Wp = (net.M[l] + 3) & ~3;
-    fwd_dispatch<NJ, RGM, SC, REV>(first, last, sm, Wp, li, y, yo, amax);
+    fwd_dispatch<NJ, RGM, SC, REV>(first, last, ls, Wp, li, y, yo, amax);
     if constexpr (REV)
       if (!last) ckpt_store<NJ, RGM>(ckbase + (l - 1) * kSlot, lane, yo);
 #pragma unroll
@@ -762,14 +825,9 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, int64_t ckpt_p
     yb[c][0][0] = cL * ub[c];
   }
 
-  // ---- reverse sweep over the hidden layers --------------------------------
-  for (int l = L - 1; l >= 1; --l) {
-    const bool first = l == 1, last = l == L - 1;
-    const int KI = first ? 4 : RP, KO = last ? 4 : RP;
-    const int Wp = (net.M[l] + 3) & ~3;
-    __syncthreads();
-    if (l == L - 1 && tid < 4) {
-      // loss sums and the output layer's s and b gradients
+  // loss sums and the output layer's s and b gradients (after a barrier)
+  auto output_record = [&]() {
+    if (tid < 4) {
       const float v = ((sm.lw[tid] + sm.lw[4 + tid]) + sm.lw[8 + tid]) + sm.lw[12 + tid];
       if (tid == 0) {
         rec[0] = kind == 0 ? v : 0.f;
@@ -782,14 +840,36 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, int64_t ckpt_p
         rec[4 + net.r_total + net.offB[L]] = v;
       }
     }
-    stage_layer<kThreads>(net, s, l, KI, KO, sm.Us, sm.Vs, sm.bs, sm.ss);
-    __syncthreads();
+  };
+  // layer l's s and b gradients, the waves' rows summed in a fixed order
+  auto layer_record = [&](const Smem& ls, int l) {
+    const int W = net.M[l], rl = net.r[l], Wm = Wmax_p;
+    for (int i = tid; i < W; i += kThreads)
+      rec[4 + net.r_total + net.offB[l] + i] =
+          ((ls.bbar[i] + ls.bbar[Wm + i]) + ls.bbar[2 * Wm + i]) + ls.bbar[3 * Wm + i];
+    for (int i = tid; i < rl; i += kThreads)
+      rec[4 + net.offS[l] + i] =
+          ((ls.sbar[i] + ls.sbar[RP + i]) + ls.sbar[2 * RP + i]) + ls.sbar[3 * RP + i];
+  };
+
+  // ---- reverse sweep over the hidden layers --------------------------------
+  for (int l = L - 1; l >= 1; --l) {
+    const bool first = l == 1, last = l == L - 1;
+    const int KI = first ? 4 : RP, KO = last ? 4 : RP;
+    const int Wp = (net.M[l] + 3) & ~3;
+    const Smem ls = layer_smem(sm, l, Wmax_p, RP);
+    if (!res) {
+      __syncthreads();
+      if (l == L - 1) output_record();
+      stage_layer<kThreads>(net, s, l, KI, KO, sm.Us, sm.Vs, sm.bs, sm.ss);
+      __syncthreads();
+    }
     if (first)
       input_jets<NJ, RGM>(net, x, t, y);
     else
       ckpt_load<NJ, RGM>(ckbase + (l - 2) * kSlot, lane, y);
-    bwd_dispatch<NJ, RGM, SC>(first, last, sm, Wp, li, lane, y, yb, wb,
-                              sm.bbar + wave * Wmax_p, amax);
+    bwd_dispatch<NJ, RGM, SC>(first, last, ls, Wp, li, lane, y, yb, wb,
+                              ls.bbar + wave * Wmax_p, amax);
     if (first)
       input_jets<NJ, RGM>(net, x, t, y);
     else
@@ -802,33 +882,35 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, int64_t ckpt_p
 #pragma unroll
         for (int c = 0; c < NJ; ++c) acc += wb[c][g] * y[c][g];
         const float tot = wave_sum4(acc, lane);
-        if ((lane & 15) == 0) sm.sbar[wave * RP + 4 * g + comp] = tot;
+        if ((lane & 15) == 0) ls.sbar[wave * RP + 4 * g + comp] = tot;
       }
     }
     if (!first) {
 #pragma unroll
       for (int g = 0; g < RGM; ++g) {
-        const f4 s4 = *reinterpret_cast<const f4*>(sm.ss + 4 * g);
+        const f4 s4 = *reinterpret_cast<const f4*>(ls.ss + 4 * g);
 #pragma unroll
         for (int c = 0; c < NJ; ++c) yb[c][g] = s4 * wb[c][g];
       }
     }
+    if (!res) {
+      __syncthreads();
+      layer_record(ls, l);
+    }
+  }
+  if (res) {
     __syncthreads();
-    // the layer's s and b gradients, waves summed in a fixed order
-    const int W = net.M[l], rl = net.r[l], Wm = Wmax_p;
-    for (int i = tid; i < W; i += kThreads)
-      rec[4 + net.r_total + net.offB[l] + i] =
-          ((sm.bbar[i] + sm.bbar[Wm + i]) + sm.bbar[2 * Wm + i]) + sm.bbar[3 * Wm + i];
-    for (int i = tid; i < rl; i += kThreads)
-      rec[4 + net.offS[l] + i] =
-          ((sm.sbar[i] + sm.sbar[RP + i]) + sm.sbar[2 * RP + i]) + sm.sbar[3 * RP + i];
+    output_record();
+    for (int l = L - 1; l >= 1; --l) layer_record(layer_smem(sm, l, Wmax_p, RP), l);
   }
   if constexpr (SC == SC_TRACK) {
     // flag the workgroup for the accurate relaunch if any lane met |a| > kFastRange
+    // (own slots: the loss sums in lw[0, 16) may still be being read)
+    float* fl = sm.lw + 4 * kWaves;
     const bool bad = __any(!(amax <= kFastRange));
-    if (lane == 0) sm.lw[wave] = bad ? 1.f : 0.f;
+    if (lane == 0) fl[wave] = bad ? 1.f : 0.f;
     __syncthreads();
-    if (tid == 0) *tile.flag = (sm.lw[0] + sm.lw[1] + sm.lw[2] + sm.lw[3]) > 0.f ? 1 : 0;
+    if (tid == 0) *tile.flag = (fl[0] + fl[1] + fl[2] + fl[3]) > 0.f ? 1 : 0;
   }
 }
 
@@ -875,16 +957,7 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP, MODE>()))) void lrnr
     if (grid.flags[blockIdx.x] == 0) return;  // only workgroups flagged by SC_TRACK
   }
   extern __shared__ float4 smem_raw[];
-  float* base = reinterpret_cast<float*>(smem_raw);
-  const int Wm = grid.Wmax_p;
-  Smem sm;
-  sm.Us = base;
-  sm.Vs = sm.Us + Wm * RP;
-  sm.bs = sm.Vs + Wm * RP;
-  sm.ss = sm.bs + Wm;
-  sm.bbar = sm.ss + RP;
-  sm.sbar = sm.bbar + kWaves * Wm;
-  sm.lw = sm.sbar + kWaves * RP;
+  const Smem sm = make_smem(reinterpret_cast<float*>(smem_raw), grid.Wmax_p, RP, grid.res_layers);
 
   const int inst_id = blockIdx.x / grid.G_inst;
   int wg = blockIdx.x - inst_id * grid.G_inst;
@@ -902,6 +975,7 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP, MODE>()))) void lrnr
   tile.rec = grid.partials + (int64_t)blockIdx.x * grid.P;
   tile.ck = grid.ckpt ? grid.ckpt + (int64_t)blockIdx.x * kWaves * grid.ckpt_per_wave : nullptr;
   tile.flag = grid.flags ? grid.flags + blockIdx.x : nullptr;
+  tile.stage_net = true;
   run_kind<RP, MODE, SC>(net, inst, grid.ckpt_per_wave, grid.Wmax_p, tile, kind, wg, s, mu, sm);
 }
 
@@ -909,7 +983,7 @@ template <int RP, int MODE, int SC>
 static hipError_t launch_one(const KNet& net, const KInst& inst, const KGrid& grid,
                              hipStream_t stream) {
   const dim3 blocks((unsigned)(grid.B * grid.G_inst)), threads(kThreads);
-  const size_t lds = fused_lds_bytes(RP, grid.Wmax_p);
+  const size_t lds = fused_lds_bytes(RP, grid.Wmax_p, grid.res_layers);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)lrnr_fused_kernel<RP, MODE, SC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

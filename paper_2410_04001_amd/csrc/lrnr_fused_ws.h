@@ -1059,27 +1059,16 @@ __global__ __launch_bounds__(kWsThreads) void lrnr_grad_ws_table_kernel(KTableGr
   }
 }
 
-__device__ __forceinline__ Smem fused_smem(float* base, int Wm, int RP) {
-  Smem sm;
-  sm.Us = base;
-  sm.Vs = sm.Us + Wm * RP;
-  sm.bs = sm.Vs + Wm * RP;
-  sm.ss = sm.bs + Wm;
-  sm.bbar = sm.ss + RP;
-  sm.sbar = sm.bbar + kWaves * Wm;
-  sm.lw = sm.sbar + kWaves * RP;
-  return sm;
-}
-
 template <int RP, int MODE, int SC>
 __global__ __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP, MODE>()))) void lrnr_table_kernel(
     KTableGrid tg) {
   extern __shared__ float4 smem_raw[];
-  const Smem sm = fused_smem(reinterpret_cast<float*>(smem_raw), tg.Wmax_p, RP);
+  const Smem sm = make_smem(reinterpret_cast<float*>(smem_raw), tg.Wmax_p, RP, tg.res_layers);
   const KTableHdr* hdr = reinterpret_cast<const KTableHdr*>(tg.table);
   const int n_tasks = hdr->n_tasks, n_tiles = hdr->n_tiles;
   float* ck = tg.ckpt ? tg.ckpt + (int64_t)blockIdx.x * kWaves * tg.ckpt_per_wave : nullptr;
+  int staged = -1;  // net_id whose factors the resident slabs hold
   for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     if constexpr (SC == SC_ACC) {
       if (tg.flags[tile] == 0) continue;  // only tiles flagged by the fast pass
@@ -1092,6 +1081,8 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP, MODE>()))) void lrnr
     kt.rec = tg.partials ? tg.partials + T->rec0 + (int64_t)r.local * T->P : nullptr;
     kt.ck = ck;
     kt.flag = tg.flags ? tg.flags + tile : nullptr;
+    kt.stage_net = T->net_id != staged || T->net_id < 0;
+    staged = T->net_id;
     run_kind<RP, MODE, SC>(T->net, T->inst, tg.ckpt_per_wave, tg.Wmax_p, kt, r.kind, r.wg,
                            T->inst.s, T->inst.mu, sm);
     __syncthreads();
@@ -1171,7 +1162,7 @@ int table_grid_rp(int mode, int Wmax_p) {
 
 template <int RP, int MODE, int SC>
 static hipError_t launch_table_one(const KTableGrid& tg, int grid, hipStream_t stream) {
-  const size_t lds = fused_lds_bytes(RP, tg.Wmax_p);
+  const size_t lds = fused_lds_bytes(RP, tg.Wmax_p, tg.res_layers);
   hipError_t e = set_lds(lrnr_table_kernel<RP, MODE, SC>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((lrnr_table_kernel<RP, MODE, SC>), dim3(grid), dim3(kThreads), lds, stream,

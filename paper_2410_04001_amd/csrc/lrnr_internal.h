@@ -58,6 +58,7 @@ struct KTile {
   float* rec;               // [P] partial sums (LOSS, GRAD, VJP)
   float* ck;                // [kWaves][ckpt_per_wave] checkpoint slab of the workgroup
   int* flag;                // 1 if the tile met |a| > kFastRange (SC_TRACK writes it)
+  bool stage_net;           // resident layers: stage the factors (else only s)
 };
 
 // Launch geometry, partial-sum records and scratch.
@@ -72,6 +73,8 @@ struct KGrid {
   float* ckpt;              // GRAD: [B * G_inst * kWaves][ckpt_per_wave]
   int64_t ckpt_per_wave;
   int* flags;               // GRAD: [B * G_inst] workgroups that met |a| > kFastRange
+  int res_layers;           // single-role kernel: hidden layers whose factors sit in LDS
+                            // together for the whole tile (0: staged layer by layer)
 };
 
 // Record layout: [0..3) loss sums by kind, [3] unused, [4, 4 + r_total) grad s,
@@ -112,7 +115,7 @@ struct KTask {
                             // kTaskFailed is or-ed in when the loss or its
                             // gradient turns non-finite (the task stops)
   int steps_max;            // no update once *step reaches this
-  int pad_;
+  int net_id;               // tasks with equal ids share one net (factors staged once)
 };
 
 // Launch-wide constants of a table launch.
@@ -124,6 +127,7 @@ struct KTableGrid {
   int64_t ckpt_per_wave;
   int* flags;               // [tile capacity]
   int Wmax_p;               // LDS layout width (>= every task's hidden widths)
+  int res_layers;           // as in KGrid (for Lmax - 1 hidden layers)
 };
 
 inline int64_t table_off_tasks(int cap) {
@@ -149,7 +153,11 @@ hipError_t launch_table_reduce(const KTableGrid& tg, int cap, int reduce_b, KAda
 
 // Supported padded ranks (compile-time tile heights of the rank dimension).
 int padded_rank(int rmax);
-size_t fused_lds_bytes(int RP, int Wmax_p);
+// LDS of the single-role kernel with n_slabs layer slabs (1: one layer staged
+// at a time); resident_layers gives the slab count that keeps all L - 1 hidden
+// layers of a net resident, or 0 when that would not fit the budget.
+size_t fused_lds_bytes(int RP, int Wmax_p, int n_slabs = 1);
+int resident_layers(int RP, int Wmax_p, int L);
 
 hipError_t launch_fused(int RP, int mode, const KNet& net, const KInst& inst,
                         const KGrid& grid, hipStream_t stream);

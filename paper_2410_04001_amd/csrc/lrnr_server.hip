@@ -104,6 +104,7 @@ struct lrnr_srv {
     tg.ckpt_per_wave = cpw;
     tg.flags = flags;
     tg.Wmax_p = Wmax_p;
+    tg.res_layers = resident_layers(RP, Wmax_p, Lmax);
     return tg;
   }
 
@@ -112,6 +113,7 @@ struct lrnr_srv {
     tg.table = etable;
     tg.off_tasks = table_off_tasks(cfg.max_slots);
     tg.Wmax_p = Wmax_p;
+    tg.res_layers = resident_layers(RP, Wmax_p, Lmax);
     return tg;
   }
 
@@ -145,6 +147,7 @@ struct lrnr_srv {
     char* base = arena + r.off;
     T = KTask{};
     T.net = md.k;
+    T.net_id = r.in.model;
     float* s = reinterpret_cast<float*>(base + r.fp.s);
     T.inst.s = s;
     T.inst.mu = reinterpret_cast<const float*>(base + r.fp.mu);
@@ -245,6 +248,7 @@ struct lrnr_srv {
       KTask& T = tp.tasks[i];
       T = KTask{};
       T.net = models[r.in.model].k;
+      T.net_id = r.in.model;
       char* base = arena + r.off;
       T.inst.s = reinterpret_cast<const float*>(base + r.fp.s);
       T.inst.xt_r = grid_xt;

@@ -134,6 +134,7 @@ int32_t plan_tasks(int mode, const lrnr_net* nets, int n_nets, const lrnr_task* 
     const KNet& k = kn[in.net];
     KTask& T = tp->tasks[t];
     T.net = k;
+    T.net_id = in.net;
     T.inst.s = in.s;
     T.inst.mu = in.mu;
     T.inst.xt_r = pts.xt_r;
@@ -256,6 +257,7 @@ int32_t lrnr_tasks_run(int32_t mode, const lrnr_net* nets, int32_t n_nets,
   tg.ckpt_per_wave = tp.ckpt_per_wave;
   tg.flags = tp.ckpt_per_wave ? reinterpret_cast<int*>(base + w.off_flags) : nullptr;
   tg.Wmax_p = tp.Wmax_p;
+  tg.res_layers = resident_layers(tp.RP, tp.Wmax_p, tp.Lmax);
   if (tp.n_tiles > 0) {
     int grid = table_grid(tp.RP, mode, tp.Wmax_p);
     if (grid <= 0) return fail(LRNR_EHIP, "occupancy query failed");

@@ -235,6 +235,57 @@ def test_tasks_empty_and_many(kind):
         assert np.all(np.isfinite(gs)) and np.all(np.isfinite(loss)), i
 
 
+@KINDS
+def test_tasks_persistent_workgroups_keep_and_switch_nets(kind):
+    """More tiles than persistent workgroups: each workgroup runs several
+    tiles in a row, of one net or of alternating nets (resident factors kept
+    or restaged).  Every task's outputs equal its one-task table bitwise, and
+    the jets agree with the single-instance entry point's."""
+    a = api()
+    hn = nets(kind)
+    dn = [a.DeviceNet.from_net(n) for n in hn]
+    ids = [0, 1, 0, 0, 1]
+    pool = [Inst(k, hn[k], 500 + i, 65536, 8192, 8192, 0.9 + 0.05 * i)
+            for i, k in enumerate(ids)]
+    cfg = a.LossCfg()
+    log(f"[case] {len(pool)} tasks of 65,536 + 8192 + 8192 points, nets {ids} ({kind})")
+
+    def run_set(sel, mode):
+        tab = a.TaskTable(dn)
+        for it in sel:
+            tab.add(it.net_id, s=it.s, mu=it.mu_d, xt_r=it.xt, x_0=it.x0, t_b=it.tb,
+                    grad_s=it.gs, grad_b=it.gb, loss=it.loss)
+        tab.run(mode, cfg)
+        torch.cuda.synchronize()
+        return [it.outputs() for it in sel]
+
+    for mode, name in ((a.MODE_GRAD, "grad"), (a.MODE_LOSS, "loss")):
+        alone = [run_set([it], mode)[0] for it in pool]
+        for order in (pool, pool[::-1]):
+            got = run_set(order, mode)
+            for it, o in zip(order, got):
+                ref = alone[pool.index(it)]
+                for x, y in zip(o, ref):
+                    assert np.array_equal(x, y, equal_nan=True), (name, pool.index(it))
+    it = pool[3]
+    l4, rgs, _ = orc.lrnr_loss(it.net, it.s_list(), it.mu.astype(np.float64), it.pts, {},
+                               with_grad=True)
+    f32 = fp32(lambda: orc.lrnr_loss(it.net, it.s_list(), it.mu, it.pts, {}, with_grad=True))
+    gs, _, loss = alone[3]
+    assert_close(loss, l4, TOL, "task 3 loss", blocks=LOSS_BLOCKS, floor=lambda: f32()[0])
+    assert_close(gs, rgs, TOL, "task 3 grad_s", blocks=s_blocks(it.net), floor=lambda: f32()[1])
+    # forward-only modes over the same tables
+    for it in pool:
+        it.jets.fill_(np.nan)
+    run(a.MODE_JETS, dn, pool, out_attr="jets")
+    for i, it in enumerate(pool):
+        sj = a.forward_jets(dn[it.net_id], it.s, it.xt)
+        torch.cuda.synchronize()
+        assert_close(it.jets.cpu().numpy(), sj.cpu().numpy(), 1e-6,
+                     f"task {i} jets vs lrnr_forward_jets")
+    log("  alone == mix bitwise (grad, loss); jets agree with lrnr_forward_jets")
+
+
 def test_tasks_invalid_arguments():
     a = api()
     from paper_2410_04001_amd import _clib as cl
