@@ -202,6 +202,7 @@ __device__ void basis_workgroup(const KBasis& kb, const KTile& tile, float* __re
     const int KI = first ? 4 : RP, KO = last ? 4 : RP;
     __syncthreads();
     stage_layer<kThreads>(net, s, l, KI, KO, sm.Us, sm.Vs, sm.bs, sm.ss);
+    stage_us<kThreads>(net, s, l, KI, sm.Uss);
     __syncthreads();
     const int Wp = (net.M[l] + 3) & ~3;
     fwd_dispatch<NJ, RGM, SC_REDO, true>(first, last, sm, Wp, li, y, yo, amax);
@@ -320,7 +321,8 @@ __attribute__((amdgpu_waves_per_eu(basis_waves_per_simd<RP>()))) void lrnr_basis
   const int Wm = grid.Wmax_p;
   Smem sm;
   sm.Us = base;
-  sm.Vs = sm.Us + Wm * RP;
+  sm.Uss = sm.Us + Wm * RP;
+  sm.Vs = sm.Uss + Wm * RP;
   sm.bs = sm.Vs + Wm * RP;
   sm.ss = sm.bs + Wm;
   sm.bbar = nullptr;
@@ -352,7 +354,7 @@ __attribute__((amdgpu_waves_per_eu(basis_waves_per_simd<RP>()))) void lrnr_basis
 }
 
 inline size_t basis_lds_bytes(int RP, int Wmax_p) {
-  return ((size_t)Wmax_p * RP * 2 + Wmax_p + RP) * sizeof(float);
+  return ((size_t)Wmax_p * RP * 3 + Wmax_p + RP) * sizeof(float);
 }
 
 }  // namespace lrnr

@@ -16,7 +16,7 @@ int table_grid_rp(int mode, int Wmax_p);
 
 size_t fused_lds_bytes(int RP, int Wmax_p, int n_slabs) {
   const size_t n = (size_t)std::max(1, n_slabs);
-  const size_t floats = n * ((size_t)Wmax_p * RP * 2 + Wmax_p + RP) +
+  const size_t floats = n * ((size_t)Wmax_p * RP * 3 + Wmax_p + RP) +
                         n * kWaves * ((size_t)Wmax_p + RP) + kWaves * 5;
   return floats * sizeof(float);
 }

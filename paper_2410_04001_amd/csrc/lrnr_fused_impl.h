@@ -390,18 +390,14 @@ __device__ __forceinline__ float layer_fwd_pass(const float* __restrict__ Us,
   return amax;
 }
 
+// Uss is U^l diag(s^l) as staged, so that the U side contracts y itself.
 template <int NJ, int RGM, int RGI, int RGO, int SC, bool PIPE, int EDGE>
-__device__ __forceinline__ void layer_fwd(const float* __restrict__ Us,
+__device__ __forceinline__ void layer_fwd(const float* __restrict__ Uss,
                                           const float* __restrict__ Vs,
-                                          const float* __restrict__ bs,
-                                          const float* __restrict__ ss, int Wp, int li,
-                                          f4 (&y)[NJ][RGM], f4 (&yo)[NJ][RGM], float& amax) {
-#pragma unroll
-  for (int g = 0; g < RGI; ++g) {
-    const f4 s4 = *reinterpret_cast<const f4*>(ss + 4 * g);
-#pragma unroll
-    for (int c = 0; c < NJ; ++c) y[c][g] *= s4;
-  }
+                                          const float* __restrict__ bs, int Wp, int li,
+                                          const f4 (&y)[NJ][RGM], f4 (&yo)[NJ][RGM],
+                                          float& amax) {
+  const float* __restrict__ Us = Uss;
   if constexpr (SC == SC_ACC) {
     layer_fwd_pass<NJ, RGM, RGI, RGO, true, PIPE, EDGE>(Us, Vs, bs, Wp, li, y, yo);
   } else {
@@ -415,18 +411,20 @@ __device__ __forceinline__ void layer_fwd(const float* __restrict__ Us,
 }
 
 // ---------------------------------------------------------------------------
-// One hidden layer, reverse: recompute a = U (s*y) + b, pull yb = dL/dy^{l+1}
-// back through V and the sin jets, write the layer's dL/db row, and return
-// wb = U^T abar (so that dL/ds = sum_c wb * y and dL/dy^l = s * wb).  The
+// One hidden layer, reverse: recompute a = (U diag(s)) y + b, pull
+// yb = dL/dy^{l+1} back through V and the sin jets, write the layer's dL/db
+// row, and return wb = U^T abar (so that dL/ds = sum_c wb * y and
+// dL/dy^l = s * wb).  The
 // loop is not software-pipelined: carrying the next group's a and zb beside
 // the current ones spilled at the two-waves-per-SIMD register budget and
 // measured 3-7 % slower than this plain loop.
 // ---------------------------------------------------------------------------
 template <int NJ, int RGM, int RGI, int RGO, bool ACC, int EDGE>
 __device__ __forceinline__ float layer_bwd_pass(const float* __restrict__ Us,
+                                                const float* __restrict__ Uss,
                                                 const float* __restrict__ Vs,
                                                 const float* __restrict__ bs, int Wp, int li,
-                                                int lane, const f4 (&ys)[NJ][RGM],
+                                                int lane, const f4 (&y)[NJ][RGM],
                                                 const f4 (&yb)[NJ][RGM], f4 (&wb)[NJ][RGM],
                                                 float* __restrict__ bbar_row) {
 #pragma unroll
@@ -437,7 +435,7 @@ __device__ __forceinline__ float layer_bwd_pass(const float* __restrict__ Us,
   float amax = 0.f;
   f4 a[NJ], zb[NJ], ab[NJ];
   for (int w0 = 0; w0 < Wp; w0 += 4) {
-    u_side<NJ, RGM, RGI, EDGE>(Us, bs, w0, li, ys, a);
+    u_side<NJ, RGM, RGI, EDGE>(Uss, bs, w0, li, y, a);
     v_rev<NJ, RGM, RGO, EDGE>(Vs, w0, li, yb, zb);
     sigma_bwd<NJ, ACC>(a, zb, ab, amax);
     const float bsum = wave_sum4(ab[0], lane);
@@ -449,27 +447,23 @@ __device__ __forceinline__ float layer_bwd_pass(const float* __restrict__ Us,
 
 template <int NJ, int RGM, int RGI, int RGO, int SC, int EDGE>
 __device__ __forceinline__ void layer_bwd(const float* __restrict__ Us,
+                                          const float* __restrict__ Uss,
                                           const float* __restrict__ Vs,
-                                          const float* __restrict__ bs,
-                                          const float* __restrict__ ss, int Wp, int li,
-                                          int lane, f4 (&y)[NJ][RGM],
+                                          const float* __restrict__ bs, int Wp, int li,
+                                          int lane, const f4 (&y)[NJ][RGM],
                                           const f4 (&yb)[NJ][RGM], f4 (&wb)[NJ][RGM],
                                           float* __restrict__ bbar_row, float& amax) {
-#pragma unroll
-  for (int g = 0; g < RGI; ++g) {
-    const f4 s4 = *reinterpret_cast<const f4*>(ss + 4 * g);
-#pragma unroll
-    for (int c = 0; c < NJ; ++c) y[c][g] *= s4;
-  }
   if constexpr (SC == SC_ACC) {
-    layer_bwd_pass<NJ, RGM, RGI, RGO, true, EDGE>(Us, Vs, bs, Wp, li, lane, y, yb, wb, bbar_row);
+    layer_bwd_pass<NJ, RGM, RGI, RGO, true, EDGE>(Us, Uss, Vs, bs, Wp, li, lane, y, yb, wb,
+                                                  bbar_row);
   } else {
-    const float m =
-        layer_bwd_pass<NJ, RGM, RGI, RGO, false, EDGE>(Us, Vs, bs, Wp, li, lane, y, yb, wb, bbar_row);
+    const float m = layer_bwd_pass<NJ, RGM, RGI, RGO, false, EDGE>(Us, Uss, Vs, bs, Wp, li, lane,
+                                                                   y, yb, wb, bbar_row);
     amax = fmaxf(amax, m);
     if constexpr (SC == SC_REDO) {
       if (__builtin_expect(__any(!(m <= kFastRange)), 0))
-        layer_bwd_pass<NJ, RGM, RGI, RGO, true, EDGE>(Us, Vs, bs, Wp, li, lane, y, yb, wb, bbar_row);
+        layer_bwd_pass<NJ, RGM, RGI, RGO, true, EDGE>(Us, Uss, Vs, bs, Wp, li, lane, y, yb, wb,
+                                                      bbar_row);
     }
   }
 }
@@ -477,13 +471,15 @@ __device__ __forceinline__ void layer_bwd(const float* __restrict__ Us,
 // ---------------------------------------------------------------------------
 // Workgroup driver
 // ---------------------------------------------------------------------------
-// LDS of a workgroup.  Per layer slab: U [Wmax_p][RP], V [Wmax_p][RP],
-// b [Wmax_p], s [RP]; then per slab the waves' b and s gradient rows.  With
+// LDS of a workgroup.  Per layer slab: U [Wmax_p][RP], U diag(s) [Wmax_p][RP],
+// V [Wmax_p][RP], b [Wmax_p], s [RP]; then per slab the waves' b and s
+// gradient rows.  With
 // one slab (lstride == 0) the layers are staged one at a time; with resident
 // layers, hidden layer l lives in slab l - 1, lstride floats apart, for the
 // whole tile.
 struct Smem {
   float* Us;
+  float* Uss;    // U diag(s)
   float* Vs;
   float* bs;
   float* ss;
@@ -495,10 +491,11 @@ struct Smem {
 
 __device__ __forceinline__ Smem make_smem(float* base, int Wm, int RP, int n_slabs) {
   const int n = n_slabs > 0 ? n_slabs : 1;
-  const int slab = Wm * RP * 2 + Wm + RP;
+  const int slab = Wm * RP * 3 + Wm + RP;
   Smem sm;
   sm.Us = base;
-  sm.Vs = sm.Us + Wm * RP;
+  sm.Uss = sm.Us + Wm * RP;
+  sm.Vs = sm.Uss + Wm * RP;
   sm.bs = sm.Vs + Wm * RP;
   sm.ss = sm.bs + Wm;
   sm.bbar = base + n * slab;
@@ -514,6 +511,7 @@ __device__ __forceinline__ Smem layer_smem(const Smem& sm, int l, int Wm, int RP
   Smem v = sm;
   const int o = (l - 1) * sm.lstride;
   v.Us += o;
+  v.Uss += o;
   v.Vs += o;
   v.bs += o;
   v.ss += o;
@@ -573,8 +571,22 @@ __device__ void stage_layer(const KNet& net, const float* __restrict__ s, int l,
     for (int i = tx; i < KI; i += NT) ss[i] = i < rl ? s[net.offS[l] + i] : 0.f;
 }
 
+// Stage U^l diag(s^l) [Wp][KI] (zero padded) for the U side, which then
+// contracts the unscaled reduced jets.
+template <int NT>
+__device__ void stage_us(const KNet& net, const float* __restrict__ s, int l, int KI,
+                         float* __restrict__ Uss) {
+  const int W = net.M[l], Wp = (W + 15) & ~15, rl = net.r[l];
+  const float* __restrict__ U = net.U + net.offU[l];
+  const float* __restrict__ sl = s + net.offS[l];
+  for (int i = threadIdx.x; i < Wp * KI; i += NT) {
+    const int w = i / KI, k = i - w * KI;
+    Uss[i] = (w < W && k < rl) ? U[w * rl + k] * sl[k] : 0.f;
+  }
+}
+
 // Resident layers: stage every hidden layer's slab (or, when the factors are
-// already there from the previous tile of the same net, only s).
+// already there from the previous tile of the same net, only s and U diag(s)).
 template <int RP>
 __device__ void stage_resident(const KNet& net, const float* __restrict__ s, bool factors,
                                const Smem& sm, int Wm) {
@@ -588,6 +600,7 @@ __device__ void stage_resident(const KNet& net, const float* __restrict__ s, boo
       const int rl = net.r[l];
       for (int i = tx; i < KI; i += kThreads) ls.ss[i] = i < rl ? s[net.offS[l] + i] : 0.f;
     }
+    stage_us<kThreads>(net, s, l, KI, ls.Uss);
   }
 }
 
@@ -617,32 +630,32 @@ __device__ __forceinline__ void fwd_dispatch(bool first, bool last, const Smem& 
                                              f4 (&yo)[NJ][RGM], float& amax) {
   constexpr int F = kEdgeFirst, LA = kEdgeLast;
   if (first && last)
-    layer_fwd<NJ, RGM, 1, 1, SC, PIPE, F | LA>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
+    layer_fwd<NJ, RGM, 1, 1, SC, PIPE, F | LA>(sm.Uss, sm.Vs, sm.bs, Wp, li, y, yo, amax);
   else if (first)
-    layer_fwd<NJ, RGM, 1, RGM, SC, PIPE, F>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
+    layer_fwd<NJ, RGM, 1, RGM, SC, PIPE, F>(sm.Uss, sm.Vs, sm.bs, Wp, li, y, yo, amax);
   else if (last)
-    layer_fwd<NJ, RGM, RGM, 1, SC, PIPE, LA>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
+    layer_fwd<NJ, RGM, RGM, 1, SC, PIPE, LA>(sm.Uss, sm.Vs, sm.bs, Wp, li, y, yo, amax);
   else
-    layer_fwd<NJ, RGM, RGM, RGM, SC, PIPE, 0>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, y, yo, amax);
+    layer_fwd<NJ, RGM, RGM, RGM, SC, PIPE, 0>(sm.Uss, sm.Vs, sm.bs, Wp, li, y, yo, amax);
 }
 
 template <int NJ, int RGM, int SC>
 __device__ __forceinline__ void bwd_dispatch(bool first, bool last, const Smem& sm, int Wp,
-                                             int li, int lane, f4 (&y)[NJ][RGM],
+                                             int li, int lane, const f4 (&y)[NJ][RGM],
                                              const f4 (&yb)[NJ][RGM], f4 (&wb)[NJ][RGM],
                                              float* bbar_row, float& amax) {
   constexpr int F = kEdgeFirst, LA = kEdgeLast;
   if (first && last)
-    layer_bwd<NJ, RGM, 1, 1, SC, F | LA>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb,
+    layer_bwd<NJ, RGM, 1, 1, SC, F | LA>(sm.Us, sm.Uss, sm.Vs, sm.bs, Wp, li, lane, y, yb, wb,
                                          bbar_row, amax);
   else if (first)
-    layer_bwd<NJ, RGM, 1, RGM, SC, F>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb,
+    layer_bwd<NJ, RGM, 1, RGM, SC, F>(sm.Us, sm.Uss, sm.Vs, sm.bs, Wp, li, lane, y, yb, wb,
                                       bbar_row, amax);
   else if (last)
-    layer_bwd<NJ, RGM, RGM, 1, SC, LA>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb,
+    layer_bwd<NJ, RGM, RGM, 1, SC, LA>(sm.Us, sm.Uss, sm.Vs, sm.bs, Wp, li, lane, y, yb, wb,
                                        bbar_row, amax);
   else
-    layer_bwd<NJ, RGM, RGM, RGM, SC, 0>(sm.Us, sm.Vs, sm.bs, sm.ss, Wp, li, lane, y, yb, wb,
+    layer_bwd<NJ, RGM, RGM, RGM, SC, 0>(sm.Us, sm.Uss, sm.Vs, sm.bs, Wp, li, lane, y, yb, wb,
                                         bbar_row, amax);
 }
 
@@ -720,6 +733,7 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, int64_t ckpt_p
     if (!res) {
       __syncthreads();
       stage_layer<kThreads>(net, s, l, KI, KO, sm.Us, sm.Vs, sm.bs, sm.ss);
+      stage_us<kThreads>(net, s, l, KI, sm.Uss);
       __syncthreads();
     }
     const int Wp = (net.M[l] + 3) & ~3;
@@ -862,6 +876,7 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, int64_t ckpt_p
       __syncthreads();
       if (l == L - 1) output_record();
       stage_layer<kThreads>(net, s, l, KI, KO, sm.Us, sm.Vs, sm.bs, sm.ss);
+      stage_us<kThreads>(net, s, l, KI, sm.Uss);
       __syncthreads();
     }
     if (first)
@@ -870,10 +885,6 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, int64_t ckpt_p
       ckpt_load<NJ, RGM>(ckbase + (l - 2) * kSlot, lane, y);
     bwd_dispatch<NJ, RGM, SC>(first, last, ls, Wp, li, lane, y, yb, wb,
                               ls.bbar + wave * Wmax_p, amax);
-    if (first)
-      input_jets<NJ, RGM>(net, x, t, y);
-    else
-      ckpt_load<NJ, RGM>(ckbase + (l - 2) * kSlot, lane, y);
     const int RGI = first ? 1 : RGM;
 #pragma unroll
     for (int g = 0; g < RGM; ++g) {
