@@ -679,12 +679,32 @@ __device__ __forceinline__ void ckpt_load(const float* __restrict__ base, int la
       y[c][g] = *reinterpret_cast<const f4*>(base + ((c * RGM + g) * 64 + lane) * 4);
 }
 
-template <int RP, int MODE, int NJ, int SC>
+// Waves per SIMD the compiler budgets registers for.  Rank tiles up to 8
+// fit two waves (256 registers) in every mode, which hides the latency of
+// the one-wave-per-point-group chain: measured 20-27 % faster for the
+// gradient at rank tile 8 than at the default budget (one wave, ~310
+// registers).  The forward-only modes (jets, value, loss) there take three
+// waves (168 registers).  So do the reverse modes of the persistent task-
+// table kernel, which always has more tiles than SIMDs in its throughput
+// forms: 168 registers with ~40 spilled outside the neuron loops, 6-7 %
+// faster per differentiation step than two waves.  The plain launch keeps
+// two: at config-3 sizes one wave per SIMD is all there is, and the spills
+// only lengthen its chain (5 % slower at three).  Rank tile 16 at two waves
+// spills heavily (2x slower).
+template <int RP, int MODE, bool TABLE>
+constexpr int fused_waves_per_simd() {
+  if (RP > 8) return 1;
+  return (MODE == MODE_GRAD || MODE == MODE_VJP) && !TABLE ? 2 : 3;
+}
+
+template <int RP, int MODE, int NJ, int SC, bool TABLE>
 __device__ void run_workgroup(const KNet& net, const KInst& inst, int64_t ckpt_per_wave,
                               int Wmax_p, const KTile& tile, int kind, int wg,
                               const float* __restrict__ s, const float* __restrict__ mu,
                               const Smem& sm) {
   constexpr bool REV = reverse_mode(MODE);
+  // the forward group loop is software-pipelined only at the two-wave budget
+  constexpr bool PIPE = REV && fused_waves_per_simd<RP, MODE, TABLE>() == 2;
   constexpr int RGM = RP / 4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 3;
   const int L = net.L;
@@ -737,7 +757,7 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, int64_t ckpt_p
       __syncthreads();
     }
     const int Wp = (net.M[l] + 3) & ~3;
-    fwd_dispatch<NJ, RGM, SC, REV>(first, last, ls, Wp, li, y, yo, amax);
+    fwd_dispatch<NJ, RGM, SC, PIPE>(first, last, ls, Wp, li, y, yo, amax);
     if constexpr (REV)
       if (!last) ckpt_store<NJ, RGM>(ckbase + (l - 1) * kSlot, lane, yo);
 #pragma unroll
@@ -927,42 +947,29 @@ __device__ void run_workgroup(const KNet& net, const KInst& inst, int64_t ckpt_p
 
 // Dispatch on the point kind: interior points carry four jets, IC/BC points
 // (and plain value evaluation) one.
-template <int RP, int MODE, int SC>
+template <int RP, int MODE, int SC, bool TABLE>
 __device__ __forceinline__ void run_kind(const KNet& net, const KInst& inst,
                                          int64_t ckpt_per_wave, int Wmax_p, const KTile& tile,
                                          int kind, int wg, const float* __restrict__ s,
                                          const float* __restrict__ mu, const Smem& sm) {
   if constexpr (MODE == MODE_VALUE) {
-    run_workgroup<RP, MODE, 1, SC>(net, inst, ckpt_per_wave, Wmax_p, tile, kind, wg, s, mu, sm);
+    run_workgroup<RP, MODE, 1, SC, TABLE>(net, inst, ckpt_per_wave, Wmax_p, tile, kind, wg, s, mu, sm);
   } else if constexpr (MODE == MODE_JETS || MODE == MODE_VJP) {
-    run_workgroup<RP, MODE, 4, SC>(net, inst, ckpt_per_wave, Wmax_p, tile, kind, wg, s, mu, sm);
+    run_workgroup<RP, MODE, 4, SC, TABLE>(net, inst, ckpt_per_wave, Wmax_p, tile, kind, wg, s, mu, sm);
   } else {
     if (kind == 0)
-      run_workgroup<RP, MODE, 4, SC>(net, inst, ckpt_per_wave, Wmax_p, tile, kind, wg, s, mu,
+      run_workgroup<RP, MODE, 4, SC, TABLE>(net, inst, ckpt_per_wave, Wmax_p, tile, kind, wg, s, mu,
                                      sm);
     else
-      run_workgroup<RP, MODE, 1, SC>(net, inst, ckpt_per_wave, Wmax_p, tile, kind, wg, s, mu,
+      run_workgroup<RP, MODE, 1, SC, TABLE>(net, inst, ckpt_per_wave, Wmax_p, tile, kind, wg, s, mu,
                                      sm);
   }
 }
 
-// Waves per SIMD the compiler budgets registers for.  Rank tiles up to 8
-// fit two waves (256 registers) in every mode, which hides the latency of
-// the one-wave-per-point-group chain: measured 20-27 % faster for the
-// gradient at rank tile 8 than at the default budget (one wave, ~310
-// registers); the forward-only modes (jets, value, loss) there take three
-// waves (168 registers, a few values spilled outside the loops; the
-// differentiation-form step, whose forward is a loss-only launch, ~2 %
-// faster).  Rank tile 16 at two waves spills heavily (2x slower).
-template <int RP, int MODE>
-constexpr int fused_waves_per_simd() {
-  if (RP > 8) return 1;
-  return MODE == MODE_GRAD || MODE == MODE_VJP ? 2 : 3;
-}
 
 template <int RP, int MODE, int SC>
 __global__ __launch_bounds__(kThreads)
-__attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP, MODE>()))) void lrnr_fused_kernel(
+__attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP, MODE, false>()))) void lrnr_fused_kernel(
     KNet net, KInst inst, KGrid grid) {
   if constexpr (SC == SC_ACC) {
     if (grid.flags[blockIdx.x] == 0) return;  // only workgroups flagged by SC_TRACK
@@ -987,7 +994,8 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP, MODE>()))) void lrnr
   tile.ck = grid.ckpt ? grid.ckpt + (int64_t)blockIdx.x * kWaves * grid.ckpt_per_wave : nullptr;
   tile.flag = grid.flags ? grid.flags + blockIdx.x : nullptr;
   tile.stage_net = true;
-  run_kind<RP, MODE, SC>(net, inst, grid.ckpt_per_wave, grid.Wmax_p, tile, kind, wg, s, mu, sm);
+  run_kind<RP, MODE, SC, false>(net, inst, grid.ckpt_per_wave, grid.Wmax_p, tile, kind, wg, s, mu,
+                                sm);
 }
 
 template <int RP, int MODE, int SC>

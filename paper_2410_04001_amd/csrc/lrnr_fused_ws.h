@@ -1061,7 +1061,7 @@ __global__ __launch_bounds__(kWsThreads) void lrnr_grad_ws_table_kernel(KTableGr
 
 template <int RP, int MODE, int SC>
 __global__ __launch_bounds__(kThreads)
-__attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP, MODE>()))) void lrnr_table_kernel(
+__attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP, MODE, true>()))) void lrnr_table_kernel(
     KTableGrid tg) {
   extern __shared__ float4 smem_raw[];
   const Smem sm = make_smem(reinterpret_cast<float*>(smem_raw), tg.Wmax_p, RP, tg.res_layers);
@@ -1083,7 +1083,7 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP, MODE>()))) void lrnr
     kt.flag = tg.flags ? tg.flags + tile : nullptr;
     kt.stage_net = T->net_id != staged || T->net_id < 0;
     staged = T->net_id;
-    run_kind<RP, MODE, SC>(T->net, T->inst, tg.ckpt_per_wave, tg.Wmax_p, kt, r.kind, r.wg,
+    run_kind<RP, MODE, SC, true>(T->net, T->inst, tg.ckpt_per_wave, tg.Wmax_p, kt, r.kind, r.wg,
                            T->inst.s, T->inst.mu, sm);
     __syncthreads();
   }

@@ -193,8 +193,8 @@ int32_t check_points(const lrnr_points* pts);
 int32_t check_cfg(const lrnr_loss_cfg* cfg, bool sref_elsewhere = false);
 
 // Persistent workgroups of a reverse-mode table launch never exceed this
-// (checkpoint slabs are sized for it).
-constexpr int kTableGridCap = 512;
+// (checkpoint slabs are sized for it): three 4-wave workgroups per CU.
+constexpr int kTableGridCap = 768;
 
 // Host image of a task table and the sizes derived from it.
 struct TablePlan {
