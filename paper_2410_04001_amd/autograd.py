@@ -83,7 +83,7 @@ class CDRLoss(torch.autograd.Function):
     """loss_i(s_i) for every instance of a CDRBatch: s [B, r_total] -> [B]."""
 
     @staticmethod
-    def forward(ctx, s, batch, recompute=True):
+    def forward(ctx, s, batch, recompute):
         s_ = s.detach()
         if recompute:
             loss = batch.loss(s_)
@@ -102,8 +102,16 @@ class CDRLoss(torch.autograd.Function):
         return gout.to(g.dtype)[:, None] * g, None, None
 
 
-def cdr_loss(s, batch, recompute=True):
-    """Per-instance CDR loss [B] of the coefficients s [B, r_total]."""
+def cdr_loss(s, batch, recompute=None):
+    """Per-instance CDR loss [B] of the coefficients s [B, r_total].
+
+    recompute: True runs the loss-only pass in the forward and the fused
+    loss + gradient pass in the backward; False runs the fused pass in the
+    forward and keeps the gradient ([B, r_total]) for the backward, one
+    launch per step instead of two.  None (default) takes False when a
+    backward can follow (grad mode on and s requires grad), else True."""
+    if recompute is None:
+        recompute = not (torch.is_grad_enabled() and s.requires_grad)
     return CDRLoss.apply(s, batch, recompute)
 
 

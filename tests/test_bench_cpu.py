@@ -44,7 +44,8 @@ def _fake_record():
         "per_mu": [{"mu": [1.0, 2.0, 3.0], "ms_per_step": 2.9}] * 8,
         "fastlrnr": {"lrnr_ms": 0.119, "fastlrnr_ms": 0.071, "speedup": 1.68, "build_s": 0.3},
         "equal_accuracy": [{"time_ratio_lrnr_over_fast": 1.68}, {"time_ratio_lrnr_over_fast": 4.7}],
-        "differentiation": {"ms_per_adam_step": 1.15, "fused_loss_grad_ms": 0.82},
+        "differentiation": {"ms_per_adam_step": 0.70, "ms_per_adam_step_recompute": 0.94,
+                            "fused_loss_grad_ms": 0.64},
         "serving": {"rates": [rate(r) for r in (50, 100, 200, 500, 1000, 2000)]},
         "meta": {"ms_per_meta_step": 1.38},
         "fidelity": {"rows": [{"r_hat": 8, "x": list(range(50))}] * 28},

@@ -172,7 +172,8 @@ def test_all_sets_empty_gives_zero():
     ((2, 37, 50, 1), 13),                   # widths not a multiple of 4, tile 16
     ((2, 100, 90, 80, 1), (2, 24, 17, 1)),  # mixed ranks, tile 24
     ((2, 64, 64, 64, 1), 32),               # tile 32
-    ((2, 48, 48, 48, 48, 48, 48, 48, 1), 5),  # depth 8, tile 8
+    ((2, 48, 48, 48, 48, 48, 48, 48, 1), 5),  # depth 8, tile 8 (all layers resident in LDS)
+    ((2, 160, 160, 160, 1), 8),             # tile 8 too wide for resident layers
     ((2, 256, 256, 1), 20),                 # widest, tile 20
 ])
 def test_net_shapes(M, rank):
