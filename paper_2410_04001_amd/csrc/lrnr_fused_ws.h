@@ -1069,14 +1069,11 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP, MODE, true>()))) voi
   const int n_tasks = hdr->n_tasks, n_tiles = hdr->n_tiles;
   float* ck = tg.ckpt ? tg.ckpt + (int64_t)blockIdx.x * kWaves * tg.ckpt_per_wave : nullptr;
   int staged = -1;  // net_id whose factors the resident slabs hold
-  for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    if constexpr (SC == SC_ACC) {
-      if (tg.flags[tile] == 0) continue;  // only tiles flagged by the fast pass
-    }
+  auto run_tile = [&](int tile) {
     const TileRef r = decode_tile(tg, n_tasks, tile);
     const KTask* T = r.task;
     if constexpr (reverse_mode(MODE))
-      if (task_finished(T)) continue;
+      if (task_finished(T)) return;
     KTile kt;
     kt.rec = tg.partials ? tg.partials + T->rec0 + (int64_t)r.local * T->P : nullptr;
     kt.ck = ck;
@@ -1084,8 +1081,21 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP, MODE, true>()))) voi
     kt.stage_net = T->net_id != staged || T->net_id < 0;
     staged = T->net_id;
     run_kind<RP, MODE, SC, true>(T->net, T->inst, tg.ckpt_per_wave, tg.Wmax_p, kt, r.kind, r.wg,
-                           T->inst.s, T->inst.mu, sm);
+                                 T->inst.s, T->inst.mu, sm);
     __syncthreads();
+  };
+  if constexpr (SC == SC_ACC) {
+    // only the tiles the fast pass flagged: a workgroup tests kThreads flags
+    // at once, so a launch with nothing flagged is one pass per workgroup
+    for (int base = blockIdx.x * kThreads; base < n_tiles; base += gridDim.x * kThreads) {
+      const int t = base + (int)threadIdx.x;
+      if (!__syncthreads_or(t < n_tiles && tg.flags[t] != 0)) continue;
+      const int end = min(base + kThreads, n_tiles);
+      for (int tile = base; tile < end; ++tile)
+        if (tg.flags[tile] != 0) run_tile(tile);
+    }
+  } else {
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) run_tile(tile);
   }
 }
 

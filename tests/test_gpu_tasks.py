@@ -286,6 +286,39 @@ def test_tasks_persistent_workgroups_keep_and_switch_nets(kind):
     log("  alone == mix bitwise (grad, loss); jets agree with lrnr_forward_jets")
 
 
+def test_tasks_large_preactivations_take_the_accurate_path():
+    """Four neurons of layer 1 of one net get zero U-rows and bias 2^25, so
+    their pre-activation is exactly 2^25 (the fast sin/cos reduction is not
+    valid there): every tile of its tasks is flagged and recomputed by the
+    accurate relaunch, which scans the flags a workgroup-width at a time.
+    Tasks of the other net are not flagged and keep the fast pass's
+    results."""
+    a = api()
+    hn = nets("narrow")
+    big = wl.make_net(np.random.Generator(np.random.PCG64(52)), [2, 64, 64, 64, 1],
+                      wl.ranks([2, 64, 64, 64, 1], 8))
+    big.U[0][:4, :] = 0.0
+    big.b[0][:4] = np.float32(2.0 ** 25)
+    hn = [hn[0], big]
+    dn = [a.DeviceNet.from_net(n) for n in hn]
+    ids = [0, 1, 0, 1]
+    pool = [Inst(k, hn[k], 600 + i, 40000, 4000, 4000) for i, k in enumerate(ids)]
+    cfg = a.LossCfg()
+    log(f"[case] task table GRAD with |a| = 2^25 in net 1, tasks {ids}")
+    run(a.MODE_GRAD, dn, pool, cfg)
+    for i in (0, 1):
+        it = pool[i]
+        gs, gb, loss = it.outputs()
+        l4, rgs, rgb = orc.lrnr_loss(it.net, it.s_list(), it.mu.astype(np.float64), it.pts, {},
+                                     with_grad=True)
+        f32 = fp32(lambda: orc.lrnr_loss(it.net, it.s_list(), it.mu, it.pts, {}, with_grad=True))
+        assert_close(loss, l4, TOL, f"task {i} loss", blocks=LOSS_BLOCKS, floor=lambda: f32()[0])
+        assert_close(gs, rgs, TOL, f"task {i} grad_s", blocks=s_blocks(it.net),
+                     floor=lambda: f32()[1])
+        assert_close(gb, rgb, TOL, f"task {i} grad_b", blocks=b_blocks(it.net),
+                     floor=lambda: f32()[2])
+
+
 def test_tasks_invalid_arguments():
     a = api()
     from paper_2410_04001_amd import _clib as cl
