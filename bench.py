@@ -1033,8 +1033,8 @@ def main():
                     help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the loss+gradient shards over points with one small all-reduce; see the "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the loss+gradient would shard over points with one small all-reduce; see the "
               "design notes)", file=sys.stderr)
         sys.exit(2)
     import torch
