@@ -155,17 +155,23 @@ hipError_t launch_reduce(const KReduce& kr, hipStream_t stream) {
 
 // ---------------------------------------------------------------------------
 // Task tables: one workgroup per task (grid-stride).  Each record element is
-// summed by one thread in the order of the two-stage reduction above (chunks
-// of kRedChunk records, then the chunk sums in order), so a task's results
-// depend only on its own records and match the single-instance path.
+// summed in the order of the two-stage reduction above (chunks of kRedChunk
+// records, then the chunk sums in order), so a task's results depend only on
+// its own records and match the single-instance path.  When the chunk sums
+// of a task fit kTablePartials doubles, every (element, chunk) pair has its
+// own thread and one thread per element then adds the chunk sums in order
+// (the same additions, a few rounds of loads instead of one per chunk);
+// otherwise one thread runs all chunks of an element.
 // ---------------------------------------------------------------------------
 constexpr int kTableReduceThreads = 256;
+constexpr int kTablePartials = 2048;
 
 __global__ __launch_bounds__(kTableReduceThreads) void table_reduce_kernel(KTableGrid tg,
                                                                            int reduce_b,
                                                                            KAdam adam) {
   __shared__ double sums[4];
   __shared__ float gsh[LRNR_MAX_LAYERS * LRNR_MAX_RANK];
+  __shared__ double part[kTablePartials];
   const KTableHdr* hdr = reinterpret_cast<const KTableHdr*>(tg.table);
   const int* start = reinterpret_cast<const int*>(tg.table + sizeof(KTableHdr));
   const KTask* tasks = reinterpret_cast<const KTask*>(tg.table + tg.off_tasks);
@@ -191,12 +197,25 @@ __global__ __launch_bounds__(kTableReduceThreads) void table_reduce_kernel(KTabl
     const float* sref = T.s_ref;
     const bool loc = T.lambda_loc != 0.f && sref != nullptr;
     const int nchunk = (G + kRedChunk - 1) / kRedChunk;
+    const bool split = nchunk * E <= kTablePartials;
+    if (split) {
+      for (int q = tid; q < nchunk * E; q += kTableReduceThreads) {
+        const int c = q / E, e = q - c * E;
+        const int r0 = c * kRedChunk, r1 = min(G, r0 + kRedChunk);
+        part[q] = ordered_sum(rec + (int64_t)r0 * P + e, P, r1 - r0);
+      }
+      __syncthreads();
+    }
     int nonfinite = 0;
     for (int e = tid; e < E; e += kTableReduceThreads) {
       double acc = 0.0;
       for (int c = 0; c < nchunk; ++c) {
-        const int r0 = c * kRedChunk, r1 = min(G, r0 + kRedChunk);
-        acc += ordered_sum(rec + (int64_t)r0 * P + e, P, r1 - r0);
+        if (split) {
+          acc += part[c * E + e];
+        } else {
+          const int r0 = c * kRedChunk, r1 = min(G, r0 + kRedChunk);
+          acc += ordered_sum(rec + (int64_t)r0 * P + e, P, r1 - r0);
+        }
       }
       if (e < 4) {
         sums[e] = acc;
