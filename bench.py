@@ -802,8 +802,9 @@ def run_serving(args, torch, api, wl):
               f"achieved {row['req_per_s']:.1f} req/s", file=sys.stderr, flush=True)
     stats = srv.stats()
     srv.close()
-    # the same stream with several steps per graph launch: fewer launches,
-    # coarser admission (a request joins between launches)
+    # the same stream with another number of steps per graph launch (more:
+    # fewer launches, coarser admission, since a request joins between
+    # launches)
     rows_multi = []
     spl = 4 if args.serve_steps_per_launch == 1 else 1
     if args.serve_rates_multi:
@@ -1023,10 +1024,14 @@ def main():
     ap.add_argument("--serve-rates", type=lambda x: [float(v) for v in x.split(",")],
                     default=[50, 100, 200, 500, 1000, 2000])
     ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--serve-steps-per-launch", type=int, default=1)
+    ap.add_argument("--serve-steps-per-launch", type=int, default=2,
+                    help="Adam steps per graph launch of the serving engine (the stream is "
+                         "replayed again at --serve-rates-multi with one step per launch, or "
+                         "four when this is one)")
     ap.add_argument("--serve-rates-multi", type=lambda x: [float(v) for v in x.split(",") if v],
                     default=[500, 1000],
-                    help="rates replayed again with 4 steps per launch (1 if the main run uses more)")
+                    help="rates replayed again with one step per launch (four when the main run "
+                         "uses one)")
     ap.add_argument("--out", default=os.path.join("gpurun_out", "bench_full.json"),
                     help="file for the full record of every leg")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -79,7 +79,7 @@ class Server:
     names one by index.  The nets' device memory must outlive the server.
     """
 
-    def __init__(self, models, K=100, steps_per_launch=1, max_slots=64, max_inflight=2,
+    def __init__(self, models, K=100, steps_per_launch=2, max_slots=64, max_inflight=2,
                  arena_bytes=1 << 30, max_tiles=1 << 16, use_graph=True, loss=None,
                  lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, grid=(256, 100)):
         self._keep = list(models)

@@ -72,7 +72,8 @@ def run_alone(models, spec, **kw):
 
 def test_serving_alone_equals_mix_bitwise(models):
     alone = {sp[0]: run_alone(models, sp) for sp in SPECS}
-    for kw in ({}, {"steps_per_launch": 4}, {"use_graph": False, "max_inflight": 3}):
+    for kw in ({}, {"steps_per_launch": 1}, {"steps_per_launch": 4},
+               {"use_graph": False, "max_inflight": 3}):
         srv = make_server(models, **kw)
         reqs = requests(srv, SPECS)
         # staggered arrivals: two now, the rest while those run
