@@ -967,9 +967,11 @@ __device__ __forceinline__ void run_kind(const KNet& net, const KInst& inst,
 }
 
 
-template <int RP, int MODE, int SC>
+// W3: the three-wave register budget of the task-table kernel, for launches
+// with more workgroups than two waves per SIMD hold at once.
+template <int RP, int MODE, int SC, bool W3 = false>
 __global__ __launch_bounds__(kThreads)
-__attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP, MODE, false>()))) void lrnr_fused_kernel(
+__attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP, MODE, W3>()))) void lrnr_fused_kernel(
     KNet net, KInst inst, KGrid grid) {
   if constexpr (SC == SC_ACC) {
     if (grid.flags[blockIdx.x] == 0) return;  // only workgroups flagged by SC_TRACK
@@ -994,22 +996,22 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<RP, MODE, false>()))) vo
   tile.ck = grid.ckpt ? grid.ckpt + (int64_t)blockIdx.x * kWaves * grid.ckpt_per_wave : nullptr;
   tile.flag = grid.flags ? grid.flags + blockIdx.x : nullptr;
   tile.stage_net = true;
-  run_kind<RP, MODE, SC, false>(net, inst, grid.ckpt_per_wave, grid.Wmax_p, tile, kind, wg, s, mu,
-                                sm);
+  run_kind<RP, MODE, SC, W3>(net, inst, grid.ckpt_per_wave, grid.Wmax_p, tile, kind, wg, s, mu,
+                             sm);
 }
 
-template <int RP, int MODE, int SC>
+template <int RP, int MODE, int SC, bool W3 = false>
 static hipError_t launch_one(const KNet& net, const KInst& inst, const KGrid& grid,
                              hipStream_t stream) {
   const dim3 blocks((unsigned)(grid.B * grid.G_inst)), threads(kThreads);
   const size_t lds = fused_lds_bytes(RP, grid.Wmax_p, grid.res_layers);
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)lrnr_fused_kernel<RP, MODE, SC>,
+    hipError_t e = hipFuncSetAttribute((const void*)lrnr_fused_kernel<RP, MODE, SC, W3>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((lrnr_fused_kernel<RP, MODE, SC>), blocks, threads, lds, stream, net, inst,
-                     grid);
+  hipLaunchKernelGGL((lrnr_fused_kernel<RP, MODE, SC, W3>), blocks, threads, lds, stream, net,
+                     inst, grid);
   return hipGetLastError();
 }
 

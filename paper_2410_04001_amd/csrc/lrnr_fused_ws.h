@@ -1220,6 +1220,13 @@ hipError_t launch_grad_ws(const KNet& net, const KInst& inst, const KGrid& grid,
   if constexpr (RP <= kWsMaxRP) ws = four_role<RP>(grid.Wmax_p);
   if (!ws) {
     if constexpr (RP <= 8) {
+      if ((int64_t)grid.B * grid.G_inst > 2 * (int64_t)device_cus()) {
+        // more workgroups than two per CU: three waves per SIMD, as in the
+        // task tables (fast pass, then the flagged workgroups recomputed)
+        hipError_t e = launch_one<RP, MODE_GRAD, SC_TRACK, true>(net, inst, grid, stream);
+        if (e != hipSuccess) return e;
+        return launch_one<RP, MODE_GRAD, SC_ACC>(net, inst, grid, stream);
+      }
       // a wave that meets |a| > kFastRange redoes that layer pass with
       // ocml's sin/cos at once: no relaunch of flagged workgroups
       return launch_one<RP, MODE_GRAD, SC_REDO>(net, inst, grid, stream);
