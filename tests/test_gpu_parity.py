@@ -262,9 +262,13 @@ def test_determinism_bitwise(width, rank):
 
 
 @NETS
-def test_batched_equals_single_bitwise(width, rank):
+@pytest.mark.parametrize("n_r", [1000, 30000])
+def test_batched_equals_single_bitwise(width, rank, n_r):
+    """With 30,000 points the five-instance launch has 815 workgroups (more
+    than two per CU: the three-wave fast pass and relaunch at rank tile 8)
+    while each single-instance launch has 163 (two waves, redo in place)."""
     a = api()
-    w = custom(25, (2, width, width, width, width, 1), rank, 1000, 125, 125)
+    w = custom(25, (2, width, width, width, width, 1), rank, n_r, n_r // 8, n_r // 8)
     net, s, pts, _ = to_dev(w)
     rng = np.random.default_rng(4)
     B = 5
