@@ -7,9 +7,9 @@
 // contraction is a v_mfma_f32_4x4x1_16b_f32 whose 16 blocks of 4 columns are
 // the 64 lanes of the wave, so the MFMA result of lane p is always point p:
 //
-//  * U side, a_c[p][w0+i] += U[w0+i][k] * (s*y_c)[p][k]: A operand lane 4b+i
-//    holds U[w0+i][k] (a row of U in LDS), B operand lane p its own (s*y)[k];
-//    accumulator GPR i holds neuron w0+i.
+//  * U side, a_c[p][w0+i] += (U diag(s))[w0+i][k] * y_c[p][k]: A operand lane
+//    4b+i holds (U diag(s))[w0+i][k] (a row staged in LDS), B operand lane p
+//    its own y[k]; accumulator GPR i holds neuron w0+i.
 //  * V side, y'_c[p][4g+i] += V[w][4g+i] * z_c[p][w]: A operand is a 4-rank
 //    slice of row w of V, B operand is z of the lane's own point; accumulator
 //    GPR i holds rank 4g+i.
@@ -17,10 +17,11 @@
 // The reduced coordinates y^l = V^lT z^{l-1} (r_l floats per jet) are the only
 // per-point state carried between layers; in the gradient mode they are
 // checkpointed to global scratch in the forward sweep and the W-wide
-// activations are recomputed in the reverse sweep.  The factors of one layer
-// are staged into LDS (zero-padded to 4-aligned widths and the compiled rank
-// tile RP), which lets the same code run the full LRNR (width M_l) and the
-// FastLRNR (width r_hat_l).
+// activations are recomputed in the reverse sweep.  The factors are staged
+// into LDS (zero-padded to 4-aligned widths and the compiled rank tile RP),
+// every hidden layer at once when they fit, else one layer at a time, which
+// lets the same code run the full LRNR (width M_l) and the FastLRNR (width
+// r_hat_l).
 #pragma once
 
 #include "lrnr_internal.h"
