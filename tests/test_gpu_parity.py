@@ -437,19 +437,24 @@ def test_fastlrnr_qdeim_matches_oracle(n_sets):
     fast.close()
 
 
-def test_fastlrnr_r32_prefix_operators_and_chain():
-    """r_hat = 32 on the 64-wide net runs past the resolved snapshot spectrum,
-    where POD modes are rounding noise in any precision and later DEIM picks
-    are arbitrary.  Checked: the picks on the resolved prefix equal the
-    oracle's; U_hat = P^T U and b_hat = P^T b exactly; the EIM reduction
-    reproduces the projected snapshot states V^{(l+1)T} z^l; and the device
-    FastLRNR loss and gradient equal the oracle's eq. 2.8 chain run on the
-    device's own reduced operators."""
+@pytest.mark.parametrize("which", ["small", "wide"])
+def test_fastlrnr_r32_prefix_operators_and_chain(which):
+    """r_hat = 32 on the 64-wide rank-8 net, and on the 256-wide rank-20 net
+    (reduced widths 32 at rank tile 20: the four-role kernel), runs past the
+    resolved snapshot spectrum, where POD modes are rounding noise in any
+    precision and later DEIM picks are arbitrary.  Checked: the picks on the
+    resolved prefix equal the oracle's; U_hat = P^T U and b_hat = P^T b
+    exactly; the EIM reduction reproduces the projected snapshot states
+    V^{(l+1)T} z^l; and the device FastLRNR loss and gradient equal the
+    oracle's eq. 2.8 chain run on the device's own reduced operators."""
     a = api()
-    w = wl.fast_case(2, n=8192)
+    if which == "small":
+        w = wl.fast_case(2, n=8192)
+    else:
+        w = wl.equal_accuracy_case(big=True, n=8192)
     xs = w.extra["xt_snap"]
     k = resolved_modes(w.net, xs)
-    log(f"[case] fastlrnr r_hat=32, resolved modes per layer {k}")
+    log(f"[case] fastlrnr {which} r_hat=32, resolved modes per layer {k}")
     net, s, pts, mu = to_dev(w)
     fast = a.FastLRNR(net, s.reshape(1, -1), torch.tensor(xs, device="cuda"), 32)
     P = fast.indices()
@@ -459,7 +464,7 @@ def test_fastlrnr_r32_prefix_operators_and_chain():
         n_eq = int(np.argmin(np.append(p == q, False)))
         agree.append(n_eq)
         assert n_eq >= min(kl, 32), (n_eq, kl, p, q)
-        assert len(set(p.tolist())) == 32 and p.min() >= 0 and p.max() < 64
+        assert len(set(p.tolist())) == 32 and p.min() >= 0 and p.max() < max(w.net.M)
     log(f"  picks equal to the oracle's: {agree} (resolved prefix {k})")
     ops = fast.operators()
     Z = orc.lrnr_hidden_values(w.net, w.net.s, xs)
@@ -476,9 +481,9 @@ def test_fastlrnr_r32_prefix_operators_and_chain():
     l4, rgs = orc.fast_loss(w.net, ops, w.net.s, w.mu[0].astype(np.float64), w.pts, {},
                             with_grad=True)
     f32 = fp32(lambda: orc.fast_loss(w.net, ops, w.net.s, w.mu[0], w.pts, {}, with_grad=True))
-    assert_close(loss.cpu().numpy(), l4, TOL, "fast r32 loss (device operators)",
+    assert_close(loss.cpu().numpy(), l4, TOL, f"fast {which} r32 loss (device operators)",
                  blocks=LOSS_BLOCKS, floor=lambda: f32()[0])
-    assert_close(gs.cpu().numpy(), rgs, TOL, "fast r32 grad_s (device operators)",
+    assert_close(gs.cpu().numpy(), rgs, TOL, f"fast {which} r32 grad_s (device operators)",
                  blocks=s_blocks(w.net), floor=lambda: f32()[1])
     fast.close()
 
