@@ -175,6 +175,7 @@ def test_all_sets_empty_gives_zero():
     ((2, 48, 48, 48, 48, 48, 48, 48, 1), 5),  # depth 8, tile 8 (all layers resident in LDS)
     ((2, 160, 160, 160, 1), 8),             # tile 8 too wide for resident layers
     ((2, 256, 256, 1), 20),                 # widest, tile 20
+    ((2, 256, 256, 256, 1), 32),            # compiled maxima: width 256, tile 32
 ])
 def test_net_shapes(M, rank):
     w = custom(31, M, rank, 700, 90, 70, mu=(11.0, 2.0, 3.5))
