@@ -9,7 +9,8 @@ width 256, rank 20, sin activation, synthetic net and points (seeded).
 The last line on stdout is one compact JSON record (the headline: metric,
 value, median ms per step, roofline, CPU baseline and one-line summaries of
 the side legs).  The full record of every leg is written to --out (default
-gpurun_out/bench_full.json); each leg prints a progress line to stderr.
+bench_full.json in the working directory); each leg prints a progress line
+to stderr.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fast]
                   [--no-equal-acc] [--no-diff] [--no-serve] [--serve-rates 50,100,...]
@@ -1032,7 +1033,7 @@ def main():
                     default=[500, 1000],
                     help="rates replayed again with one step per launch (four when the main run "
                          "uses one)")
-    ap.add_argument("--out", default=os.path.join("gpurun_out", "bench_full.json"),
+    ap.add_argument("--out", default="bench_full.json",
                     help="file for the full record of every leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
