@@ -279,13 +279,22 @@ __device__ __forceinline__ void sincos_hw(float x, float& s, float& c) {
   c = __builtin_amdgcn_cosf(rev);
 }
 
+// Range tracking for the sin/cos path choice uses IEEE maximum (gfx950's
+// v_maximum3_f32), not fmaxf: it needs no canonicalising moves of its inputs
+// (three VALU instructions per neuron group instead of seven), and a NaN
+// pre-activation makes the running maximum NaN, which fails every range test
+// and so takes the accurate path (fmaxf would drop it).
+__device__ __forceinline__ float vmax(float a, float b) {
+  return __builtin_elementwise_maximum(a, b);
+}
+
 // sin/cos of the four pre-activations of a neuron group: the hardware path
 // when every lane of the wave is within kHwRange (a wave-uniform choice),
 // otherwise the Cody-Waite polynomial; ACC selects ocml's sincosf.
 template <bool ACC>
 __device__ __forceinline__ void sincos4(const f4& a, f4& sn, f4& cs, float& amax) {
-  const float m = fmaxf(fmaxf(fabsf(a[0]), fabsf(a[1])), fmaxf(fabsf(a[2]), fabsf(a[3])));
-  amax = fmaxf(amax, m);
+  const float m = vmax(vmax(fabsf(a[0]), fabsf(a[1])), vmax(fabsf(a[2]), fabsf(a[3])));
+  amax = vmax(amax, m);
   if constexpr (ACC) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -403,7 +412,7 @@ __device__ __forceinline__ void layer_fwd(const float* __restrict__ Uss,
     layer_fwd_pass<NJ, RGM, RGI, RGO, true, PIPE, EDGE>(Us, Vs, bs, Wp, li, y, yo);
   } else {
     const float m = layer_fwd_pass<NJ, RGM, RGI, RGO, false, PIPE, EDGE>(Us, Vs, bs, Wp, li, y, yo);
-    amax = fmaxf(amax, m);
+    amax = vmax(amax, m);
     if constexpr (SC == SC_REDO) {
       if (__builtin_expect(__any(!(m <= kFastRange)), 0))
         layer_fwd_pass<NJ, RGM, RGI, RGO, true, PIPE, EDGE>(Us, Vs, bs, Wp, li, y, yo);
@@ -460,7 +469,7 @@ __device__ __forceinline__ void layer_bwd(const float* __restrict__ Us,
   } else {
     const float m = layer_bwd_pass<NJ, RGM, RGI, RGO, false, EDGE>(Us, Uss, Vs, bs, Wp, li, lane,
                                                                    y, yb, wb, bbar_row);
-    amax = fmaxf(amax, m);
+    amax = vmax(amax, m);
     if constexpr (SC == SC_REDO) {
       if (__builtin_expect(__any(!(m <= kFastRange)), 0))
         layer_bwd_pass<NJ, RGM, RGI, RGO, true, EDGE>(Us, Uss, Vs, bs, Wp, li, lane, y, yb, wb,

@@ -111,8 +111,8 @@ __device__ __forceinline__ void xget2(const float* __restrict__ slot, int lane, 
 // whole wave is within kHwRange, else the Cody-Waite polynomial)
 template <int NJ>
 __device__ __forceinline__ void sigma_fwd2(const f2 (&a)[NJ], f2 (&z)[NJ], float& amax) {
-  const float m = fmaxf(fabsf(a[0][0]), fabsf(a[0][1]));
-  amax = fmaxf(amax, m);
+  const float m = vmax(fabsf(a[0][0]), fabsf(a[0][1]));
+  amax = vmax(amax, m);
   f2 sn, cs;
   if (__all(m <= kHwRange)) {
 #pragma unroll
@@ -146,8 +146,8 @@ template <int N>
 __device__ __forceinline__ void sigma_fwd_vals(const f2 (&a)[N], f2 (&z)[N], float& amax) {
   float m = 0.f;
 #pragma unroll
-  for (int i = 0; i < N; ++i) m = fmaxf(m, fmaxf(fabsf(a[i][0]), fabsf(a[i][1])));
-  amax = fmaxf(amax, m);
+  for (int i = 0; i < N; ++i) m = vmax(m, vmax(fabsf(a[i][0]), fabsf(a[i][1])));
+  amax = vmax(amax, m);
   if (__all(m <= kHwRange)) {
 #pragma unroll
     for (int i = 0; i < N; ++i)
@@ -176,8 +176,8 @@ __device__ __forceinline__ void sigma_bwd_vals(const f4 (&a)[N], const f4 (&zb)[
   float m = 0.f;
 #pragma unroll
   for (int i = 0; i < N; ++i)
-    m = fmaxf(m, fmaxf(fmaxf(fabsf(a[i][0]), fabsf(a[i][1])), fmaxf(fabsf(a[i][2]), fabsf(a[i][3]))));
-  amax = fmaxf(amax, m);
+    m = vmax(m, vmax(vmax(fabsf(a[i][0]), fabsf(a[i][1])), vmax(fabsf(a[i][2]), fabsf(a[i][3]))));
+  amax = vmax(amax, m);
   if (__all(m <= kHwRange)) {
 #pragma unroll
     for (int i = 0; i < N; ++i)
