@@ -196,6 +196,29 @@ def test_large_preactivations_take_the_accurate_path(width, rank):
     check_loss_grad(w, tag="large |a|")
 
 
+def test_nan_point_stays_local():
+    """A NaN input makes the running |a| maximum of its wave NaN (IEEE
+    maximum propagates it), which fails the range test, so that wave takes
+    the accurate sin/cos path.  The NaN point's jets are NaN; every other
+    point's jets, including its wave neighbours on the accurate path, match
+    the oracle."""
+    a = api()
+    w = wl.small_lrnr(0, 300)
+    xt = w.pts.xt_r[:300].copy()
+    xt[77, 0] = np.nan
+    log("[case] jets with one NaN point (index 77 of 300)")
+    net = a.DeviceNet.from_net(w.net)
+    s = torch.tensor(w.net.s_flat(), device="cuda")
+    jets = a.forward_jets(net, s, torch.tensor(xt, device="cuda")).cpu().numpy()
+    assert np.all(np.isnan(jets[:, 77]))
+    ok = np.ones(len(xt), bool)
+    ok[77] = False
+    assert np.all(np.isfinite(jets[:, ok]))
+    ref = orc.lrnr_forward_jets(w.net, w.net.s, xt[ok])
+    for c, name, tol in ((0, "u", TOL), (1, "u_x", TOL), (2, "u_t", TOL), (3, "u_xx", TOL_XX)):
+        assert_close(jets[c][ok], ref[c], tol, f"NaN neighbours {name}")
+
+
 def test_big_net_reduced_points():
     w = wl.big_lrnr(1, 2048)
     check_jets(w, tag="big 2048")
