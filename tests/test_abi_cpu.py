@@ -28,6 +28,25 @@ def test_library_exports_every_declared_symbol(lib):
         assert hasattr(lib, n), n
 
 
+def test_missing_library_fails_loudly():
+    """Without the built library the binding raises (there is no fallback);
+    checked in a child interpreter so this process keeps its loaded library."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("from paper_2410_04001_amd import _clib as cl\n"
+            "cl.LIB_PATH = '/nonexistent/liblrnr.so'\n"
+            "try:\n"
+            "    cl.lib()\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "raised:" in r.stdout and "is missing" in r.stdout, r.stdout
+
+
 def _net(L=5, M=(2, 64, 64, 64, 64, 1), r=(0, 2, 8, 8, 8, 1), ptr=16):
     n = cl.LrnrNet()
     n.L = L
