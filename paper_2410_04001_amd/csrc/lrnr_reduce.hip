@@ -81,28 +81,30 @@ __global__ void reduce_stage2(KReduce kr) {
 }
 
 // Both stages in one launch when an instance has at most kRedFusedChunks
-// chunks: thread (ex, c) of a block forms the stage-1 sum of chunk c for
-// element blockIdx.x * kRedFusedElems + ex, and thread (ex, 0) then adds the
-// chunk sums in chunk order.  The additions and their order are those of
+// chunks (2048 records; the working-size launch has 1408 in 44 chunks):
+// thread (ex, c) of a block (ex fastest, so that a wave reads 16 consecutive
+// elements of four chunk rows) forms the stage-1 sum of chunk c for element
+// blockIdx.x * kRedFusedElems + ex, and thread (ex, 0) then adds the chunk
+// sums in chunk order.  The additions and their order are those of
 // reduce_stage1 + reduce_stage2, so the results are the same bits.
-constexpr int kRedFusedElems = 8;
-constexpr int kRedFusedChunks = 32;
+constexpr int kRedFusedElems = 16;
+constexpr int kRedFusedChunks = 64;
 
 __global__ __launch_bounds__(kRedFusedElems* kRedFusedChunks) void reduce_fused(KReduce kr) {
-  __shared__ double part[kRedFusedElems][kRedFusedChunks];
+  __shared__ double part[kRedFusedChunks][kRedFusedElems];
   __shared__ double col[kRedFusedElems];
-  const int ex = threadIdx.x / kRedFusedChunks, c = threadIdx.x % kRedFusedChunks;
+  const int ex = threadIdx.x % kRedFusedElems, c = threadIdx.x / kRedFusedElems;
   const int e = blockIdx.x * kRedFusedElems + ex, inst = blockIdx.y;
   const int P = kr.P;
   if (e < kr.E && c < kr.nchunk) {
     const int r0 = c * kRedChunk, r1 = min(kr.G_inst, r0 + kRedChunk);
     const float* base = kr.partials + ((int64_t)inst * kr.G_inst + r0) * P + e;
-    part[ex][c] = ordered_sum(base, P, r1 - r0);
+    part[c][ex] = ordered_sum(base, P, r1 - r0);
   }
   __syncthreads();
   if (c == 0) {
     double acc = 0.0;
-    for (int k = 0; k < kr.nchunk; ++k) acc += part[ex][k];
+    for (int k = 0; k < kr.nchunk; ++k) acc += part[k][ex];
     col[ex] = acc;
   }
   __syncthreads();
@@ -138,9 +140,10 @@ hipError_t launch_reduce(const KReduce& kr, hipStream_t stream) {
   const int bx = 256;
   const int gx = (kr.E + bx - 1) / bx;
   if (kr.nchunk > 0 && kr.nchunk <= kRedFusedChunks) {
+    // threads for the chunks in use, rounded up to whole waves
     const int gf = (kr.E + kRedFusedElems - 1) / kRedFusedElems;
-    hipLaunchKernelGGL(reduce_fused, dim3(gf, kr.B), dim3(kRedFusedElems * kRedFusedChunks), 0,
-                       stream, kr);
+    const int nt = (kRedFusedElems * kr.nchunk + 63) & ~63;
+    hipLaunchKernelGGL(reduce_fused, dim3(gf, kr.B), dim3(nt), 0, stream, kr);
     return hipGetLastError();
   }
   if (kr.nchunk > 0) {
